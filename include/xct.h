@@ -1,0 +1,164 @@
+/*
+ * xct.h - C ABI of the MI355X (gfx950) parallel-beam filtered back-projection
+ * library (libxct.so).
+ *
+ * The operation is the per-slice reconstruction stage of the paper "Paradigm
+ * Shift in Infrastructure Inspection Technology" (arXiv 2505.13955): every
+ * detector row of a parallel-beam scan is reconstructed into its own slice
+ * (Section V-A a, scan-row partition) by filtered back-projection, i.e. a
+ * ramp-type filter along each projection row followed by back-projection of
+ * the filtered rows (Section IV-B; Section V-A c, stage 2, cost
+ * O(N_p N_x N_y) per slice).  Arguments follow the paper's Table I: N_p
+ * projection angles, N_c detector channels, N_x x N_y slices.
+ *
+ * Conventions (the paper states none; these are the ones this library fixes):
+ *   pixel (row i, col j) centre  x_j = (j - (N_x-1)/2) * pixel_size
+ *                                y_i = (i - (N_y-1)/2) * pixel_size
+ *   detector coordinate (bins)   u = (x cos th + y sin th) / det_pitch + center
+ *   hat weight                   K(t) = max(0, 1 - |t|), bin n centred at u = n
+ *   A[(k,n),(i,j)]               = K(u_k(x_j, y_i) - n)
+ * Rows are zero outside [0, N_c): taps there contribute nothing (no clamping).
+ *
+ * Layouts (row-major, contiguous, no padding):
+ *   sinogram  [S][N_p][N_c]   detector fastest
+ *   image     [S][N_y][N_x]   column (x) fastest
+ *
+ * Ownership: every array pointer is a DEVICE pointer owned by the caller,
+ * except xct_geometry.angles, a HOST array read during the call only.  Work is
+ * enqueued on `stream` (a hipStream_t; NULL = the null stream) and the call
+ * returns without synchronising; results are visible after the stream syncs.
+ * The library keeps one cache of per-geometry device tables (trigonometry,
+ * filter spectra), filled on first use with a blocking upload and released by
+ * xct_cache_clear(); it allocates nothing else.
+ *
+ * Errors: every argument is validated before any HIP call and nothing is
+ * written when a call returns an error.  Return value 0 = XCT_OK, otherwise a
+ * negative xct_status.  A failed HIP launch or allocation returns XCT_EHIP;
+ * faults inside kernels surface at the caller's next synchronisation.
+ * All entry points are thread-safe.
+ */
+#ifndef XCT_H
+#define XCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define XCT_VERSION 10000 /* 1.0.0 */
+
+typedef enum {
+    XCT_OK = 0,
+    XCT_EINVAL = -1,     /* null pointer, size <= 0, non-finite or non-positive geometry */
+    XCT_EDTYPE = -2,     /* dtype or window id not supported by this entry point */
+    XCT_EWORKSPACE = -3, /* workspace null, misaligned or smaller than required */
+    XCT_ETOOBIG = -4,    /* a size beyond the documented limits */
+    XCT_EHIP = -5        /* the HIP runtime reported an error */
+} xct_status;
+
+typedef enum { XCT_F32 = 0, XCT_F16 = 1, XCT_BF16 = 2 } xct_dtype;
+
+/* Filter windows W(nu) applied to the ramp |nu| on |nu| <= 1/2 (cut-off at
+ * the detector Nyquist frequency).  The spatial kernels are the inverse DTFTs
+ *   Ram-Lak:      h[0] = 1/4, h[even] = 0, h[odd n] = -1/(pi^2 n^2)
+ *   Shepp-Logan:  h[n] = 2 / (pi^2 (1 - 4 n^2))                (W = sinc)
+ *   Hann:         h[n] = h_RL[n]/2 + (h_RL[n-1] + h_RL[n+1])/4  (W = (1+cos 2 pi nu)/2) */
+typedef enum { XCT_RAM_LAK = 0, XCT_SHEPP_LOGAN = 1, XCT_HANN = 2 } xct_window;
+
+typedef void *xct_stream; /* hipStream_t */
+
+/* One slice geometry (Table I: N_p, N_c, N_x, N_y). */
+typedef struct {
+    int32_t n_angles;      /* N_p >= 1                                       */
+    int32_t n_det;         /* N_c >= 1                                       */
+    int32_t nx, ny;        /* N_x, N_y >= 1                                  */
+    double det_pitch;      /* detector bin width, > 0                        */
+    double pixel_size;     /* pixel width, > 0                               */
+    double center;         /* rotation axis in detector bins (finite)        */
+    const double *angles;  /* HOST [n_angles] projection angles in radians  */
+} xct_geometry;
+
+/* Limits: N_c <= 8192 for the filter (FFT length 2*N_c-1 rounded up to a power
+ * of two, at most 16384, held in one workgroup's LDS); N_x, N_y, N_c <= 65536,
+ * N_p <= 1 << 20; S * max(N_p*N_c, N_x*N_y) < 2^62; 1/16 <= pixel_size/det_pitch <= 16;
+ * |center| <= 1e6; the forward projector takes at most 65535 slices per call.
+ * Larger sizes return XCT_ETOOBIG. */
+
+/* Windowed ramp filter of every sinogram row (Section IV-B, first step):
+ *   filtered[s][k][n] = (1/det_pitch) sum_{m=0}^{N_c-1} h_W[n-m] sino[s][k][m]
+ * Linear (not circular) convolution: the row is zero outside the detector.
+ * Only n_angles, n_det and det_pitch of `g` are used (angles may be NULL).
+ * sino: [n_slices][N_p][N_c] of sino_t; filtered: same shape, of filtered_t
+ * (F16 / BF16 outputs are rounded to nearest even).  In-place
+ * (filtered == sino) is allowed when both dtypes are equal. */
+int xct_filter(const xct_geometry *g, int32_t n_slices, const void *sino, int32_t sino_t,
+               void *filtered, int32_t filtered_t, int32_t window, xct_stream stream);
+
+/* Back-projection (Section IV-B, second step) and the adjoint of the forward
+ * projector:
+ *   image[s][i][j] = (accumulate ? image[s][i][j] : 0)
+ *                    + scale * sum_k sum_n sino[s][k][n] K(u_k(x_j, y_i) - n)
+ * Linear interpolation along the detector in FP32; FP16 / BF16 sinograms are
+ * widened exactly and everything after is FP32.  FBP uses scale = pi / N_p;
+ * the exact transpose of xct_forward_project uses scale = pixel^2 / pitch. */
+int xct_backproject(const xct_geometry *g, int32_t n_slices, const void *sino, int32_t sino_t,
+                    float *image, float scale, int32_t accumulate, xct_stream stream);
+
+/* Pixel-driven forward projector, the exact transpose of the back-projector:
+ *   sino[s][k][n] = (pixel^2 / pitch) sum_{i,j} image[s][i][j] K(u_k(x_j, y_i) - n)
+ * FP32 only.  Deterministic (gather form, no atomics). */
+int xct_forward_project(const xct_geometry *g, int32_t n_slices, const float *image,
+                        float *sino, xct_stream stream);
+
+/* One slab of slices sharing a geometry, for xct_fbp_batch. */
+typedef struct {
+    xct_geometry geom;
+    int32_t n_slices;
+    const void *sino; /* device [n_slices][N_p][N_c] of the batch's sino_t  */
+    float *image;     /* device [n_slices][N_y][N_x] FP32, overwritten      */
+} xct_slab;
+
+/* Bytes of device workspace xct_fbp_batch needs for these slabs when the
+ * filtered rows are kept as `filtered_t` (0 on invalid arguments). */
+size_t xct_fbp_workspace_bytes(const xct_slab *slabs, int32_t n_slabs, int32_t filtered_t);
+
+/* Filtered back-projection of a batch of slabs, possibly of different sizes
+ * (the single-GPU analogue of the paper's grouped row partitions, Section
+ * V-A b):
+ *   image = (pi / N_p) A^T ((1/det_pitch) h_W * sino)      per slice
+ * The filter runs over every row of every slab into `workspace` (stored as
+ * filtered_t), then ONE persistent back-projection launch walks all
+ * (slab, slice, tile) work items, largest cost first.  workspace: device,
+ * 256-byte aligned, at least xct_fbp_workspace_bytes(); its contents are
+ * scratch.  n_slabs <= 16. */
+int xct_fbp_batch(const xct_slab *slabs, int32_t n_slabs, int32_t sino_t, int32_t window,
+                  int32_t filtered_t, void *workspace, size_t workspace_bytes,
+                  xct_stream stream);
+
+/* FP64 reductions of FP32 vectors for the adjoint-identity and gradient
+ * checks:  *result = sum_i (double)a[i] * (double)b[i]           (xct_dot_f64)
+ *          *result = sum_i ((double)a[i] - (double)b[i])^2       (xct_sqdist_f64)
+ * a, b: device [n]; result: DEVICE pointer to one double.  Deterministic
+ * (fixed reduction tree).  workspace: device, >= xct_reduce_workspace_bytes(). */
+size_t xct_reduce_workspace_bytes(int64_t n);
+int xct_dot_f64(const float *a, const float *b, int64_t n, double *result, void *workspace,
+                size_t workspace_bytes, xct_stream stream);
+int xct_sqdist_f64(const float *a, const float *b, int64_t n, double *result, void *workspace,
+                   size_t workspace_bytes, xct_stream stream);
+
+/* Static description of a status code. */
+const char *xct_status_string(int status);
+/* XCT_VERSION of the loaded library. */
+int xct_version(void);
+/* hipError_t of the most recent XCT_EHIP on the calling thread (0 if none). */
+int xct_last_hip_error(void);
+/* Frees the cached per-geometry device tables (call with no work in flight). */
+void xct_cache_clear(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XCT_H */

@@ -1,0 +1,547 @@
+// C ABI of libxct.so: argument validation, per-geometry device tables and
+// dispatch of the filter, back-projection, forward-projection and reduction
+// kernels.  See include/xct.h for the contract of every entry point.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "xct_internal.h"
+
+using namespace xct;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_fail(hipError_t e)
+{
+    g_last_hip = (int)e;
+    return XCT_EHIP;
+}
+
+bool dtype_ok(int t) { return t == XCT_F32 || t == XCT_F16 || t == XCT_BF16; }
+size_t dtype_size(int t) { return t == XCT_F32 ? 4 : 2; }
+
+// ---------------------------------------------------------------- validation
+
+int check_geometry(const xct_geometry *g, bool need_angles)
+{
+    if (!g) return XCT_EINVAL;
+    if (g->n_angles <= 0 || g->n_det <= 0 || g->nx <= 0 || g->ny <= 0) return XCT_EINVAL;
+    if (!std::isfinite(g->det_pitch) || !(g->det_pitch > 0)) return XCT_EINVAL;
+    if (!std::isfinite(g->pixel_size) || !(g->pixel_size > 0)) return XCT_EINVAL;
+    if (!std::isfinite(g->center)) return XCT_EINVAL;
+    if (need_angles) {
+        if (!g->angles) return XCT_EINVAL;
+        for (int k = 0; k < g->n_angles; ++k)
+            if (!std::isfinite(g->angles[k])) return XCT_EINVAL;
+    }
+    if (g->n_det > 65536 || g->nx > 65536 || g->ny > 65536 || g->n_angles > (1 << 20))
+        return XCT_ETOOBIG;
+    const double ratio = g->pixel_size / g->det_pitch;
+    if (ratio > 16.0 || ratio < 1.0 / 16.0) return XCT_ETOOBIG;
+    if (std::fabs(g->center) > 1e6) return XCT_ETOOBIG;
+    return XCT_OK;
+}
+
+int check_slices(const xct_geometry *g, int32_t n_slices)
+{
+    if (n_slices <= 0) return XCT_EINVAL;
+    const double lim = 4.0e18;
+    if ((double)n_slices * g->n_angles * g->n_det > lim) return XCT_ETOOBIG;
+    if ((double)n_slices * g->nx * g->ny > lim) return XCT_ETOOBIG;
+    return XCT_OK;
+}
+
+// ---------------------------------------------------------------- device tables
+
+struct GeoTables {
+    float2 *cs = nullptr;
+    double2 *csd = nullptr;
+};
+
+struct FilterTables {
+    float2 *tw = nullptr;
+    float *H = nullptr;
+};
+
+std::mutex g_mu;
+std::unordered_map<std::string, GeoTables> g_geo;
+std::unordered_map<std::string, FilterTables> g_filt;
+
+template <typename T>
+void key_append(std::string &k, const T &v)
+{
+    k.append(reinterpret_cast<const char *>(&v), sizeof(T));
+}
+
+int current_device(int *dev)
+{
+    hipError_t e = hipGetDevice(dev);
+    return e == hipSuccess ? XCT_OK : hip_fail(e);
+}
+
+// cos/sin of every angle times pixel/pitch, in FP32 (inner loops) and FP64
+// (window anchors), rounded once from FP64 host trigonometry.
+int geo_tables(const xct_geometry *g, GeoTables *out)
+{
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    const double r = g->pixel_size / g->det_pitch;
+    std::string key;
+    key_append(key, dev);
+    key_append(key, r);
+    key.append(reinterpret_cast<const char *>(g->angles), sizeof(double) * g->n_angles);
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_geo.find(key);
+    if (it != g_geo.end()) {
+        *out = it->second;
+        return XCT_OK;
+    }
+    const int n = g->n_angles;
+    std::vector<float2> cs(n);
+    std::vector<double2> csd(n);
+    for (int k = 0; k < n; ++k) {
+        const double c = std::cos(g->angles[k]) * r, s = std::sin(g->angles[k]) * r;
+        csd[k] = make_double2(c, s);
+        cs[k] = make_float2((float)c, (float)s);
+    }
+    GeoTables t;
+    hipError_t e = hipMalloc(&t.cs, sizeof(float2) * n);
+    if (e == hipSuccess) e = hipMalloc(&t.csd, sizeof(double2) * n);
+    if (e == hipSuccess) e = hipMemcpy(t.cs, cs.data(), sizeof(float2) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(t.csd, csd.data(), sizeof(double2) * n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (t.cs) (void)hipFree(t.cs);
+        if (t.csd) (void)hipFree(t.csd);
+        return hip_fail(e);
+    }
+    g_geo.emplace(key, t);
+    *out = t;
+    return XCT_OK;
+}
+
+// Spatial ramp kernel taps h_W[n] (inverse DTFT of |nu| W(nu) on |nu| <= 1/2).
+double ramp_tap(int window, long n)
+{
+    auto rl = [](long m) -> double {
+        if (m == 0) return 0.25;
+        if (m % 2 == 0) return 0.0;
+        return -1.0 / (M_PI * M_PI * (double)m * (double)m);
+    };
+    if (window == XCT_RAM_LAK) return rl(n);
+    if (window == XCT_SHEPP_LOGAN) return 2.0 / (M_PI * M_PI * (1.0 - 4.0 * (double)n * (double)n));
+    return 0.5 * rl(n) + 0.25 * (rl(n - 1) + rl(n + 1));
+}
+
+// In-place iterative radix-2 FFT in FP64 (forward, e^{-2 pi i k n / L}).
+void host_fft(std::vector<std::complex<double>> &a)
+{
+    const size_t L = a.size();
+    for (size_t i = 1, j = 0; i < L; ++i) {
+        size_t bit = L >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(a[i], a[j]);
+    }
+    for (size_t len = 2; len <= L; len <<= 1) {
+        const size_t h = len >> 1;
+        for (size_t k = 0; k < h; ++k) {
+            const double ang = -2.0 * M_PI * (double)k / (double)len;
+            const std::complex<double> w(std::cos(ang), std::sin(ang));
+            for (size_t i = 0; i < L; i += len) {
+                const std::complex<double> u = a[i + k], v = a[i + k + h] * w;
+                a[i + k] = u + v;
+                a[i + k + h] = u - v;
+            }
+        }
+    }
+}
+
+int fft_length(int nc, int *log2L)
+{
+    int L = 64, lg = 6;
+    while (L < 2 * nc - 1) {
+        L <<= 1;
+        ++lg;
+    }
+    *log2L = lg;
+    return L;
+}
+
+// Twiddles exp(-2 pi i e / L) and the filter spectrum H = DFT_L(h_W placed
+// circularly) / (L pitch), both rounded once from FP64.
+int filter_tables(int nc, int window, double pitch, FilterTables *out, int *L_out, int *lg_out)
+{
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    int lg;
+    const int L = fft_length(nc, &lg);
+    std::string key;
+    key_append(key, dev);
+    key_append(key, nc);
+    key_append(key, window);
+    key_append(key, pitch);
+    *L_out = L;
+    *lg_out = lg;
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_filt.find(key);
+    if (it != g_filt.end()) {
+        *out = it->second;
+        return XCT_OK;
+    }
+    std::vector<std::complex<double>> h(L, 0.0);
+    for (long d = -(long)(nc - 1); d <= (long)(nc - 1); ++d)
+        h[(size_t)((d % L + L) % L)] = ramp_tap(window, d);
+    host_fft(h);
+    std::vector<float> H(L);
+    for (int k = 0; k < L; ++k) H[k] = (float)(h[k].real() / ((double)L * pitch));
+    std::vector<float2> tw(L);
+    for (int e = 0; e < L; ++e) {
+        const double ang = 2.0 * M_PI * (double)e / (double)L;
+        tw[e] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
+    }
+    FilterTables t;
+    hipError_t e = hipMalloc(&t.tw, sizeof(float2) * L);
+    if (e == hipSuccess) e = hipMalloc(&t.H, sizeof(float) * L);
+    if (e == hipSuccess) e = hipMemcpy(t.tw, tw.data(), sizeof(float2) * L, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(t.H, H.data(), sizeof(float) * L, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (t.tw) (void)hipFree(t.tw);
+        if (t.H) (void)hipFree(t.H);
+        return hip_fail(e);
+    }
+    g_filt.emplace(key, t);
+    *out = t;
+    return XCT_OK;
+}
+
+int device_cus()
+{
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cus[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+        cus[dev] = n;
+    }
+    return cus[dev];
+}
+
+// ---------------------------------------------------------------- back-projection plan
+
+// Window entries per angle for a 64-pixel tile: the detector footprint of the
+// tile spans 63 (|C| + |S|) <= 63 sqrt(2) pixel/pitch bins; 3 more cover the
+// floor, the right tap and the one-bin margin of the anchor.
+int window_entries(double ratio) { return (int)std::ceil(63.0 * std::sqrt(2.0) * ratio + 1e-3) + 3; }
+
+bool symmetric_ok(const xct_geometry *g)
+{
+    if (g->nx != g->ny || (g->nx & 1) || (g->n_angles & 1)) return false;
+    const double m = 2.0 * g->center;
+    if (std::fabs(m - std::nearbyint(m)) > 1e-9) return false;
+    const int H = g->n_angles / 2;
+    for (int k = 0; k < H; ++k)
+        if (std::fabs(g->angles[k + H] - g->angles[k] - 0.5 * M_PI) > 1e-9) return false;
+    return true;
+}
+
+struct BPJob {
+    const xct_geometry *g;
+    GeoTables t;
+    int32_t n_slices;
+    const void *sino;
+    float *image;
+    float scale;
+    int32_t accumulate;
+    bool sym;
+};
+
+int tiles_of(const BPJob &j, int *tx, int *ty)
+{
+    if (j.sym) {
+        const int h = j.g->nx / 2;
+        *tx = *ty = (h + kTile - 1) / kTile;
+    } else {
+        *tx = (j.g->nx + kTile - 1) / kTile;
+        *ty = (j.g->ny + kTile - 1) / kTile;
+    }
+    return XCT_OK;
+}
+
+constexpr size_t kGenericStageBytes = 32 * 1024;
+constexpr size_t kSymStageBytes = 36 * 1024;
+
+// Launch one back-projection over jobs that all take the same kernel
+// (all symmetric or all generic).  counter != nullptr makes it persistent.
+int launch_bp_jobs(std::vector<BPJob> jobs, int dtype, unsigned int *counter, hipStream_t s)
+{
+    if (jobs.empty()) return XCT_OK;
+    const bool sym = jobs[0].sym;
+    // largest cost per item first (items of one slab cost the same)
+    std::stable_sort(jobs.begin(), jobs.end(),
+                     [](const BPJob &a, const BPJob &b) { return a.g->n_angles > b.g->n_angles; });
+    BPBatch b;
+    std::memset(&b, 0, sizeof(b));
+    int W = 0;
+    int64_t items = 0;
+    for (size_t i = 0; i < jobs.size(); ++i) {
+        const BPJob &j = jobs[i];
+        BPSlab &sl = b.slab[i];
+        int tx, ty;
+        tiles_of(j, &tx, &ty);
+        sl.sino = j.sino;
+        sl.image = j.image;
+        sl.cs = j.t.cs;
+        sl.csd = j.t.csd;
+        sl.center = j.g->center;
+        sl.item_begin = items;
+        sl.n_angles = j.g->n_angles;
+        sl.n_det = j.g->n_det;
+        sl.nx = j.g->nx;
+        sl.ny = j.g->ny;
+        sl.n_slices = j.n_slices;
+        sl.tiles_x = tx;
+        sl.tiles_y = ty;
+        sl.mirror = sym ? (int32_t)std::nearbyint(2.0 * j.g->center) : 0;
+        sl.scale = j.scale;
+        sl.accumulate = j.accumulate;
+        items += (int64_t)tx * ty * j.n_slices;
+        W = std::max(W, window_entries(j.g->pixel_size / j.g->det_pitch));
+    }
+    if (items >= (int64_t)1 << 31) return XCT_ETOOBIG;
+    b.n_slabs = (int32_t)jobs.size();
+    b.total_items = items;
+    b.win = W;
+    b.counter = counter;
+    size_t lds;
+    if (sym) {
+        b.kb = (int)std::max<size_t>(1, kSymStageBytes / (64 * (size_t)W + 24));
+        lds = bp_sym_lds_bytes(W, b.kb);
+    } else {
+        b.kb = (int)std::max<size_t>(1, std::min<size_t>(64, kGenericStageBytes / (8 * (size_t)W + 16)));
+        lds = bp_generic_lds_bytes(W, b.kb);
+    }
+    if (lds > 160 * 1024) return XCT_ETOOBIG;
+    int grid;
+    if (counter) {
+        const int per_cu = bp_max_blocks_per_cu(sym, dtype, lds);
+        grid = (int)std::min<int64_t>(items, (int64_t)per_cu * device_cus());
+        b.xcd_remap = 0;
+    } else {
+        grid = (int)items;
+        b.xcd_remap = (items % 8 == 0) ? 1 : 0;
+    }
+    hipError_t e = sym ? launch_bp_sym(b, dtype, grid, lds, s) : launch_bp_generic(b, dtype, grid, lds, s);
+    return e == hipSuccess ? XCT_OK : hip_fail(e);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+// ================================================================ C ABI
+
+extern "C" {
+
+const char *xct_status_string(int status)
+{
+    switch (status) {
+    case XCT_OK: return "ok";
+    case XCT_EINVAL: return "invalid argument";
+    case XCT_EDTYPE: return "unsupported dtype or window";
+    case XCT_EWORKSPACE: return "workspace missing, misaligned or too small";
+    case XCT_ETOOBIG: return "size beyond the supported limits";
+    case XCT_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+int xct_version(void) { return XCT_VERSION; }
+
+int xct_last_hip_error(void) { return g_last_hip; }
+
+void xct_cache_clear(void)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    for (auto &kv : g_geo) {
+        (void)hipFree(kv.second.cs);
+        (void)hipFree(kv.second.csd);
+    }
+    for (auto &kv : g_filt) {
+        (void)hipFree(kv.second.tw);
+        (void)hipFree(kv.second.H);
+    }
+    g_geo.clear();
+    g_filt.clear();
+}
+
+int xct_filter(const xct_geometry *g, int32_t n_slices, const void *sino, int32_t sino_t,
+               void *filtered, int32_t filtered_t, int32_t window, xct_stream stream)
+{
+    if (int rc = check_geometry(g, false)) return rc;
+    if (int rc = check_slices(g, n_slices)) return rc;
+    if (!sino || !filtered) return XCT_EINVAL;
+    if (!dtype_ok(sino_t) || !dtype_ok(filtered_t)) return XCT_EDTYPE;
+    if (window < XCT_RAM_LAK || window > XCT_HANN) return XCT_EDTYPE;
+    if (sino == filtered && sino_t != filtered_t) return XCT_EINVAL;
+    if (g->n_det > kMaxFFT / 2) return XCT_ETOOBIG;
+    FilterTables ft;
+    int L, lg;
+    if (int rc = filter_tables(g->n_det, window, g->det_pitch, &ft, &L, &lg)) return rc;
+    FilterArgs a;
+    a.in = sino;
+    a.out = filtered;
+    a.tw = ft.tw;
+    a.H = ft.H;
+    a.rows = (int64_t)n_slices * g->n_angles;
+    a.nc = g->n_det;
+    a.L = L;
+    a.log2L = lg;
+    hipError_t e = launch_filter(a, sino_t, filtered_t, (hipStream_t)stream);
+    return e == hipSuccess ? XCT_OK : hip_fail(e);
+}
+
+int xct_backproject(const xct_geometry *g, int32_t n_slices, const void *sino, int32_t sino_t,
+                    float *image, float scale, int32_t accumulate, xct_stream stream)
+{
+    if (int rc = check_geometry(g, true)) return rc;
+    if (int rc = check_slices(g, n_slices)) return rc;
+    if (!sino || !image) return XCT_EINVAL;
+    if (!dtype_ok(sino_t)) return XCT_EDTYPE;
+    if (!std::isfinite(scale)) return XCT_EINVAL;
+    BPJob j;
+    j.g = g;
+    j.n_slices = n_slices;
+    j.sino = sino;
+    j.image = image;
+    j.scale = scale;
+    j.accumulate = accumulate ? 1 : 0;
+    j.sym = symmetric_ok(g);
+    if (int rc = geo_tables(g, &j.t)) return rc;
+    return launch_bp_jobs({j}, sino_t, nullptr, (hipStream_t)stream);
+}
+
+int xct_forward_project(const xct_geometry *g, int32_t n_slices, const float *image, float *sino,
+                        xct_stream stream)
+{
+    if (int rc = check_geometry(g, true)) return rc;
+    if (int rc = check_slices(g, n_slices)) return rc;
+    if (!image || !sino) return XCT_EINVAL;
+    if (n_slices > 65535) return XCT_ETOOBIG;
+    GeoTables t;
+    if (int rc = geo_tables(g, &t)) return rc;
+    FPArgs a;
+    a.image = image;
+    a.sino = sino;
+    a.csd = t.csd;
+    a.center = g->center;
+    a.scale = (float)(g->pixel_size * g->pixel_size / g->det_pitch);
+    a.n_angles = g->n_angles;
+    a.n_det = g->n_det;
+    a.nx = g->nx;
+    a.ny = g->ny;
+    a.n_slices = n_slices;
+    hipError_t e = launch_forward(a, (hipStream_t)stream);
+    return e == hipSuccess ? XCT_OK : hip_fail(e);
+}
+
+static int check_slabs(const xct_slab *slabs, int32_t n_slabs, bool need_data)
+{
+    if (!slabs || n_slabs <= 0) return XCT_EINVAL;
+    if (n_slabs > kMaxSlabs) return XCT_ETOOBIG;
+    for (int i = 0; i < n_slabs; ++i) {
+        if (int rc = check_geometry(&slabs[i].geom, true)) return rc;
+        if (int rc = check_slices(&slabs[i].geom, slabs[i].n_slices)) return rc;
+        if (slabs[i].geom.n_det > kMaxFFT / 2) return XCT_ETOOBIG;
+        if (need_data && (!slabs[i].sino || !slabs[i].image)) return XCT_EINVAL;
+    }
+    return XCT_OK;
+}
+
+size_t xct_fbp_workspace_bytes(const xct_slab *slabs, int32_t n_slabs, int32_t filtered_t)
+{
+    if (check_slabs(slabs, n_slabs, false) || !dtype_ok(filtered_t)) return 0;
+    size_t bytes = 256;  // work counters
+    for (int i = 0; i < n_slabs; ++i) {
+        const xct_geometry &g = slabs[i].geom;
+        bytes += align256((size_t)slabs[i].n_slices * g.n_angles * g.n_det * dtype_size(filtered_t));
+    }
+    return bytes;
+}
+
+int xct_fbp_batch(const xct_slab *slabs, int32_t n_slabs, int32_t sino_t, int32_t window,
+                  int32_t filtered_t, void *workspace, size_t workspace_bytes, xct_stream stream)
+{
+    if (int rc = check_slabs(slabs, n_slabs, true)) return rc;
+    if (!dtype_ok(sino_t) || !dtype_ok(filtered_t)) return XCT_EDTYPE;
+    if (window < XCT_RAM_LAK || window > XCT_HANN) return XCT_EDTYPE;
+    const size_t need = xct_fbp_workspace_bytes(slabs, n_slabs, filtered_t);
+    if (!workspace || ((uintptr_t)workspace & 255) || workspace_bytes < need) return XCT_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+
+    char *ws = static_cast<char *>(workspace);
+    unsigned int *counters = reinterpret_cast<unsigned int *>(ws);
+    size_t off = 256;
+    std::vector<BPJob> sym_jobs, gen_jobs;
+    for (int i = 0; i < n_slabs; ++i) {
+        const xct_slab &sl = slabs[i];
+        const xct_geometry *g = &sl.geom;
+        void *filt = ws + off;
+        off += align256((size_t)sl.n_slices * g->n_angles * g->n_det * dtype_size(filtered_t));
+        if (int rc = xct_filter(g, sl.n_slices, sl.sino, sino_t, filt, filtered_t, window, stream))
+            return rc;
+        BPJob j;
+        j.g = g;
+        j.n_slices = sl.n_slices;
+        j.sino = filt;
+        j.image = sl.image;
+        j.scale = (float)(M_PI / g->n_angles);
+        j.accumulate = 0;
+        j.sym = symmetric_ok(g);
+        if (int rc = geo_tables(g, &j.t)) return rc;
+        (j.sym ? sym_jobs : gen_jobs).push_back(j);
+    }
+    hipError_t e = launch_fill_u32(counters, 2, 0u, s);
+    if (e != hipSuccess) return hip_fail(e);
+    if (int rc = launch_bp_jobs(sym_jobs, filtered_t, counters, s)) return rc;
+    return launch_bp_jobs(gen_jobs, filtered_t, counters + 1, s);
+}
+
+size_t xct_reduce_workspace_bytes(int64_t n)
+{
+    if (n <= 0) return 0;
+    return sizeof(double) * (size_t)reduce_blocks(n);
+}
+
+static int reduce_common(const float *a, const float *b, int64_t n, double *result, void *workspace,
+                         size_t workspace_bytes, int sqdist, xct_stream stream)
+{
+    if (!a || !b || !result || n <= 0) return XCT_EINVAL;
+    if (!workspace || ((uintptr_t)workspace & 7) || workspace_bytes < xct_reduce_workspace_bytes(n))
+        return XCT_EWORKSPACE;
+    hipError_t e = launch_reduce(a, b, n, result, static_cast<double *>(workspace), reduce_blocks(n),
+                                 sqdist, (hipStream_t)stream);
+    return e == hipSuccess ? XCT_OK : hip_fail(e);
+}
+
+int xct_dot_f64(const float *a, const float *b, int64_t n, double *result, void *workspace,
+                size_t workspace_bytes, xct_stream stream)
+{
+    return reduce_common(a, b, n, result, workspace, workspace_bytes, 0, stream);
+}
+
+int xct_sqdist_f64(const float *a, const float *b, int64_t n, double *result, void *workspace,
+                   size_t workspace_bytes, xct_stream stream)
+{
+    return reduce_common(a, b, n, result, workspace, workspace_bytes, 1, stream);
+}
+
+}  // extern "C"

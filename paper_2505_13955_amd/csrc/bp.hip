@@ -1,0 +1,410 @@
+// Back-projection kernels for gfx950.
+//
+// Back-projection (Section IV-B, second step of FBP; cost O(N_p N_x N_y) per
+// slice, Section V-A c) sums, for every pixel, the linearly interpolated value
+// of every filtered projection row at the pixel's detector coordinate
+//   u_k(x, y) = x C_k + y S_k + c,   C_k = cos(th_k) pix/pitch, S_k = sin(th_k) pix/pitch.
+//
+// Work decomposition.  A workgroup of 256 threads owns a 64 x 64 pixel tile
+// and walks all angles in LDS stages.  For each angle of a stage the part of
+// the row the tile can touch (a window of W ~ 63 sqrt(2) + 3 bins) is copied
+// into LDS once, pre-paired as (q[n], q[n+1] - q[n]) so that the inner loop
+// needs one 8-byte LDS read and one FMA per interpolation.  Each thread keeps
+// 16 pixels (a 4 x 4 lattice with stride 16) in registers; a wavefront covers
+// an 8 x 8 pixel block, whose detector footprint spans at most 12 bins, so its
+// LDS reads hit distinct banks or broadcast.
+//
+// Precision.  Detector coordinates are formed relative to the window start,
+// which the window-anchor step computes in FP64 per (tile, angle); the FP32
+// value that reaches the inner loop is then below W and carries ~1e-5 bin of
+// rounding even at 8192 bins.  Filtered rows stored as FP16 / BF16 are widened
+// exactly while staging; interpolation and accumulation are FP32 throughout.
+//
+// Two kernels:
+//  * bp_generic: any geometry (angles, centre, rectangular slices).
+//  * bp_sym:     square slices of even size, angle sets closed under
+//    th -> th + pi/2 (N_p even, th_{k+N_p/2} = th_k + pi/2) and 2c integral.
+//    Then the detector coordinate of pixel Q at th_k also gives, through the
+//    quarter-turn rotation R(x, y) = (y, -x) and the mirror u -> 2c - u of
+//    the detector, the coordinates of R^2 Q at th_k and of R^3 Q and R Q at
+//    th_k + pi/2.  One coordinate, floor and fraction then serve four updates,
+//    read from four windows interleaved in LDS (two 16-byte reads).  The
+//    workgroup owns a tile of the top-left quadrant and its three rotations.
+#include "xct_internal.h"
+
+namespace xct {
+
+template <typename T>
+__device__ __forceinline__ float load_elem(const T *p, int64_t i);
+template <>
+__device__ __forceinline__ float load_elem<float>(const float *p, int64_t i) { return p[i]; }
+template <>
+__device__ __forceinline__ float load_elem<f16_t>(const f16_t *p, int64_t i) { return (float)p[i]; }
+template <>
+__device__ __forceinline__ float load_elem<bf16_t>(const bf16_t *p, int64_t i)
+{
+    return __uint_as_float((uint32_t)p[i].bits << 16);
+}
+
+// Zero-extended row element: q[n] for n in [0, nc), else 0.
+template <typename T>
+__device__ __forceinline__ float row_elem(const T *row, int n, int nc)
+{
+    return (n >= 0 && n < nc) ? load_elem(row, n) : 0.0f;
+}
+
+// The batch descriptor is the kernel's only argument, so it sits at offset 0
+// of the kernarg segment.  Reading it through the segment pointer keeps the
+// dynamically indexed slab table in constant memory (scalar loads) instead of
+// a per-lane private copy.
+__device__ __forceinline__ const BPBatch &kernarg_batch(const BPBatch &)
+{
+    return *(const BPBatch *)__builtin_amdgcn_kernarg_segment_ptr();
+}
+
+__device__ __forceinline__ void select_slab(const BPBatch &b, int s, BPSlab &out) { out = b.slab[s]; }
+
+__device__ __forceinline__ int find_slab(const BPBatch &b, int64_t item)
+{
+    int s = 0;
+#pragma unroll
+    for (int i = 1; i < kMaxSlabs; ++i)
+        if (i < b.n_slabs && item >= b.slab[i].item_begin) s = i;
+    return s;
+}
+
+// Next work item of this workgroup: the block index (optionally remapped so
+// that consecutive items share one XCD's L2), or a grab from the persistent
+// counter.  Returns a value >= total when the workgroup is done.
+__device__ __forceinline__ int64_t next_item(const BPBatch &b, int64_t *slot, int iter)
+{
+    if (b.counter) {
+        if (threadIdx.x == 0) *slot = (int64_t)atomicAdd(b.counter, 1u);
+        __syncthreads();
+        int64_t it = *slot;
+        __syncthreads();
+        return it;
+    }
+    if (iter > 0) return b.total_items;
+    int64_t bid = blockIdx.x;
+    if (b.xcd_remap) {
+        // blocks are dispatched round-robin over the 8 XCDs; give XCD x the
+        // contiguous item range [x*n/8, (x+1)*n/8)
+        int64_t per = b.total_items >> 3;
+        bid = (bid & 7) * per + (bid >> 3);
+    }
+    return bid;
+}
+
+// Pixel lattice of one thread inside a 64 x 64 tile: a wave covers an 8 x 8
+// block, the four waves a 16 x 16 block, and the lattice repeats with stride 16.
+__device__ __forceinline__ void thread_lattice(int tid, int &px, int &py)
+{
+    px = (tid & 7) | (((tid >> 6) & 1) << 3);
+    py = ((tid >> 3) & 7) | ((tid >> 7) << 3);
+}
+
+// ---------------------------------------------------------------- generic
+
+size_t bp_generic_lds_bytes(int win, int kb)
+{
+    return (size_t)kb * sizeof(float4) + (size_t)kb * win * sizeof(float2);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBPThreads) void bp_generic_kernel(BPBatch arg)
+{
+    const BPBatch &b = kernarg_batch(arg);
+    extern __shared__ float4 lds4[];
+    __shared__ int64_t item_slot;
+    const int kb = b.kb, W = b.win;
+    float4 *par = lds4;                          // (frac anchor, C, S, window start)
+    float2 *win = reinterpret_cast<float2 *>(lds4 + kb);
+    const int tid = threadIdx.x;
+    int px, py;
+    thread_lattice(tid, px, py);
+    const float dxo = px - 31.5f, dyo = py - 31.5f;
+
+    for (int iter = 0;; ++iter) {
+        const int64_t item = next_item(b, &item_slot, iter);
+        if (item >= b.total_items) break;
+        BPSlab sl;
+        select_slab(b, find_slab(b, item), sl);
+        const int64_t local = item - sl.item_begin;
+        const int tiles = sl.tiles_x * sl.tiles_y;
+        const int z = (int)(local / tiles);
+        const int t = (int)(local - (int64_t)z * tiles);
+        const int ty = t / sl.tiles_x, tx = t - ty * sl.tiles_x;
+        const int i0 = ty * kTile, j0 = tx * kTile;
+        const double xc = j0 + 31.5 - 0.5 * (sl.nx - 1);
+        const double yc = i0 + 31.5 - 0.5 * (sl.ny - 1);
+        const int Np = sl.n_angles, Nc = sl.n_det;
+        const T *q = static_cast<const T *>(sl.sino) + (int64_t)z * Np * Nc;
+
+        float acc[16];
+#pragma unroll
+        for (int p = 0; p < 16; ++p) acc[p] = 0.0f;
+
+        for (int k0 = 0; k0 < Np; k0 += kb) {
+            const int nk = min(kb, Np - k0);
+            __syncthreads();
+            if (tid < nk) {
+                const double2 cd = sl.csd[k0 + tid];
+                const double U = xc * cd.x + yc * cd.y + sl.center;
+                const double E = 31.5 * (fabs(cd.x) + fabs(cd.y));
+                const double B = floor(U - E) - 1.0;
+                const float2 cf = sl.cs[k0 + tid];
+                par[tid] = make_float4((float)(U - B), cf.x, cf.y, __int_as_float((int)B));
+            }
+            __syncthreads();
+            for (int e = tid; e < nk * W; e += kBPThreads) {
+                const int kk = e / W, m = e - kk * W;
+                const int n = __float_as_int(par[kk].w) + m;
+                const T *row = q + (int64_t)(k0 + kk) * Nc;
+                const float a0 = row_elem(row, n, Nc);
+                const float a1 = row_elem(row, n + 1, Nc);
+                win[e] = make_float2(a0, a1 - a0);
+            }
+            __syncthreads();
+            for (int kk = 0; kk < nk; ++kk) {
+                const float4 p = par[kk];
+                const float2 *w = win + kk * W;
+                const float c16 = 16.0f * p.y, s16 = 16.0f * p.z;
+                float ur = p.x + dxo * p.y + dyo * p.z;
+#pragma unroll
+                for (int bb = 0; bb < 4; ++bb) {
+                    float u = ur;
+#pragma unroll
+                    for (int aa = 0; aa < 4; ++aa) {
+                        const int n0 = (int)u;
+                        const float tt = __builtin_amdgcn_fractf(u);
+                        const float2 v = w[n0];
+                        acc[bb * 4 + aa] += fmaf(tt, v.y, v.x);
+                        u += c16;
+                    }
+                    ur += s16;
+                }
+            }
+        }
+
+        float *img = sl.image + (int64_t)z * sl.nx * sl.ny;
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) {
+#pragma unroll
+            for (int aa = 0; aa < 4; ++aa) {
+                const int i = i0 + py + 16 * bb, j = j0 + px + 16 * aa;
+                if (i < sl.ny && j < sl.nx) {
+                    const int64_t idx = (int64_t)i * sl.nx + j;
+                    float v = sl.scale * acc[bb * 4 + aa];
+                    if (sl.accumulate) v += img[idx];
+                    img[idx] = v;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- symmetric
+
+// LDS stage: per angle pair kk, params (fbA, fbB, C, S) and window starts
+// (B_A, B_B), then two groups (A, B) of W entries; entry m of a group holds
+// 8 floats: [fwd row k | mirrored row k | fwd row k+H | mirrored row k+H],
+// each an (a, d) pair.
+size_t bp_sym_lds_bytes(int win, int kb)
+{
+    return ((size_t)kb + ((size_t)kb + 1) / 2) * sizeof(float4) + (size_t)kb * 2 * win * 2 * sizeof(float4);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBPThreads) void bp_sym_kernel(BPBatch arg)
+{
+    const BPBatch &b = kernarg_batch(arg);
+    extern __shared__ float4 lds4[];
+    __shared__ int64_t item_slot;
+    const int kb = b.kb, W = b.win;
+    float4 *par = lds4;
+    int2 *wstart = reinterpret_cast<int2 *>(lds4 + kb);
+    float4 *win = lds4 + kb + (kb * sizeof(int2) + sizeof(float4) - 1) / sizeof(float4);
+    const int tid = threadIdx.x;
+    int px, py;
+    thread_lattice(tid, px, py);
+    const float dxo = px - 31.5f, dyo = py - 31.5f;
+
+    for (int iter = 0;; ++iter) {
+        const int64_t item = next_item(b, &item_slot, iter);
+        if (item >= b.total_items) break;
+        BPSlab sl;
+        select_slab(b, find_slab(b, item), sl);
+        const int64_t local = item - sl.item_begin;
+        const int tiles = sl.tiles_x * sl.tiles_y;
+        const int z = (int)(local / tiles);
+        const int t = (int)(local - (int64_t)z * tiles);
+        const int ty = t / sl.tiles_x, tx = t - ty * sl.tiles_x;
+        const int N = sl.nx, half = N >> 1;
+        const int i0 = ty * kTile, j0 = tx * kTile;
+        const double xc = j0 + 31.5 - 0.5 * (N - 1);
+        const double yc = i0 + 31.5 - 0.5 * (N - 1);
+        const int Np = sl.n_angles, Nc = sl.n_det, H = Np >> 1, M = sl.mirror;
+        const T *q = static_cast<const T *>(sl.sino) + (int64_t)z * Np * Nc;
+
+        float acc[4][16];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int p = 0; p < 16; ++p) acc[r][p] = 0.0f;
+
+        for (int k0 = 0; k0 < H; k0 += kb) {
+            const int nk = min(kb, H - k0);
+            __syncthreads();
+            if (tid < nk) {
+                const double2 cd = sl.csd[k0 + tid];
+                const double E = 31.5 * (fabs(cd.x) + fabs(cd.y));
+                const double UA = xc * cd.x + yc * cd.y + sl.center;   // Q at th_k
+                const double UB = yc * cd.x - xc * cd.y + sl.center;   // R Q at th_k
+                const double BA = floor(UA - E) - 1.0, BB = floor(UB - E) - 1.0;
+                const float2 cf = sl.cs[k0 + tid];
+                par[tid] = make_float4((float)(UA - BA), (float)(UB - BB), cf.x, cf.y);
+                wstart[tid] = make_int2((int)BA, (int)BB);
+            }
+            __syncthreads();
+            for (int e = tid; e < nk * 2 * W; e += kBPThreads) {
+                const int kk = e / (2 * W);
+                const int rem = e - kk * 2 * W;
+                const int g = rem >= W;
+                const int m = rem - g * W;
+                const int2 ws = wstart[kk];
+                const int n = (g ? ws.y : ws.x) + m;
+                const int rn = M - n;
+                const T *rk = q + (int64_t)(k0 + kk) * Nc;
+                const T *rh = q + (int64_t)(k0 + kk + H) * Nc;
+                const float f0 = row_elem(rk, n, Nc), f1 = row_elem(rk, n + 1, Nc);
+                const float m0 = row_elem(rk, rn, Nc), m1 = row_elem(rk, rn - 1, Nc);
+                const float h0 = row_elem(rh, n, Nc), h1 = row_elem(rh, n + 1, Nc);
+                const float g0 = row_elem(rh, rn, Nc), g1 = row_elem(rh, rn - 1, Nc);
+                win[2 * e] = make_float4(f0, f1 - f0, m0, m1 - m0);
+                win[2 * e + 1] = make_float4(h0, h1 - h0, g0, g1 - g0);
+            }
+            __syncthreads();
+            for (int kk = 0; kk < nk; ++kk) {
+                const float4 p = par[kk];
+                const float C = p.z, S = p.w;
+                const float4 *wa = win + (size_t)kk * 4 * W;
+                const float4 *wb = wa + 2 * W;
+                const float c16 = 16.0f * C, s16 = 16.0f * S;
+                float ua_r = p.x + dxo * C + dyo * S;   // u(Q, th_k) - B_A
+                float ub_r = p.y + dyo * C - dxo * S;   // u(R Q, th_k) - B_B
+#pragma unroll
+                for (int bb = 0; bb < 4; ++bb) {
+                    float ua = ua_r, ub = ub_r;
+#pragma unroll
+                    for (int aa = 0; aa < 4; ++aa) {
+                        const int na = (int)ua, nb = (int)ub;
+                        const float ta = __builtin_amdgcn_fractf(ua);
+                        const float tb = __builtin_amdgcn_fractf(ub);
+                        const float4 a0 = wa[2 * na], a1 = wa[2 * na + 1];
+                        const float4 b0 = wb[2 * nb], b1 = wb[2 * nb + 1];
+                        const int pi = bb * 4 + aa;
+                        acc[0][pi] += fmaf(ta, a0.y, a0.x) + fmaf(tb, b1.y, b1.x);  // Q
+                        acc[2][pi] += fmaf(ta, a0.w, a0.z) + fmaf(tb, b1.w, b1.z);  // R^2 Q
+                        acc[3][pi] += fmaf(ta, a1.y, a1.x) + fmaf(tb, b0.w, b0.z);  // R^3 Q
+                        acc[1][pi] += fmaf(ta, a1.w, a1.z) + fmaf(tb, b0.y, b0.x);  // R Q
+                        ua += c16;
+                        ub -= s16;
+                    }
+                    ua_r += s16;
+                    ub_r += c16;
+                }
+            }
+        }
+
+        float *img = sl.image + (int64_t)z * N * N;
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) {
+#pragma unroll
+            for (int aa = 0; aa < 4; ++aa) {
+                const int i = i0 + py + 16 * bb, j = j0 + px + 16 * aa;
+                if (i < half && j < half) {
+                    const int pi = bb * 4 + aa;
+                    // Q = (i, j); R Q = (N-1-j, i); R^2 Q = (N-1-i, N-1-j); R^3 Q = (j, N-1-i)
+                    const int64_t idx[4] = {(int64_t)i * N + j, (int64_t)(N - 1 - j) * N + i,
+                                            (int64_t)(N - 1 - i) * N + (N - 1 - j),
+                                            (int64_t)j * N + (N - 1 - i)};
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        float v = sl.scale * acc[r][pi];
+                        if (sl.accumulate) v += img[idx[r]];
+                        img[idx[r]] = v;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+// Opt in to more than 64 KiB of dynamic LDS only when a launch needs it.
+template <typename K>
+static hipError_t prepare(K kernel, size_t lds)
+{
+    (void)hipGetLastError();  // report only what this launch does
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <typename T>
+static hipError_t launch_generic_t(const BPBatch &b, int grid, size_t lds, hipStream_t s)
+{
+    hipError_t e = prepare(bp_generic_kernel<T>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(bp_generic_kernel<T>, dim3(grid), dim3(kBPThreads), lds, s, b);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_sym_t(const BPBatch &b, int grid, size_t lds, hipStream_t s)
+{
+    hipError_t e = prepare(bp_sym_kernel<T>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(bp_sym_kernel<T>, dim3(grid), dim3(kBPThreads), lds, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_bp_generic(const BPBatch &b, int dtype, int grid, size_t lds, hipStream_t s)
+{
+    if (dtype == XCT_F32) return launch_generic_t<float>(b, grid, lds, s);
+    if (dtype == XCT_F16) return launch_generic_t<f16_t>(b, grid, lds, s);
+    return launch_generic_t<bf16_t>(b, grid, lds, s);
+}
+
+hipError_t launch_bp_sym(const BPBatch &b, int dtype, int grid, size_t lds, hipStream_t s)
+{
+    if (dtype == XCT_F32) return launch_sym_t<float>(b, grid, lds, s);
+    if (dtype == XCT_F16) return launch_sym_t<f16_t>(b, grid, lds, s);
+    return launch_sym_t<bf16_t>(b, grid, lds, s);
+}
+
+int bp_max_blocks_per_cu(bool sym, int dtype, size_t lds)
+{
+    int n = 0;
+    hipError_t e;
+    if (sym) {
+        if (dtype == XCT_F32)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bp_sym_kernel<float>, kBPThreads, lds);
+        else if (dtype == XCT_F16)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bp_sym_kernel<f16_t>, kBPThreads, lds);
+        else
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bp_sym_kernel<bf16_t>, kBPThreads, lds);
+    } else {
+        if (dtype == XCT_F32)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bp_generic_kernel<float>, kBPThreads, lds);
+        else if (dtype == XCT_F16)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bp_generic_kernel<f16_t>, kBPThreads, lds);
+        else
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bp_generic_kernel<bf16_t>, kBPThreads, lds);
+    }
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+}  // namespace xct

@@ -1,0 +1,208 @@
+// Windowed ramp filter of sinogram rows (Section IV-B, first step of FBP).
+//
+// The filter is a linear convolution of each detector row with the spatial
+// kernel h_W of the window, zero outside the detector:
+//   q[n] = (1/pitch) sum_{m=0}^{N_c-1} h_W[n-m] p[m].
+// With the row zero-padded to L >= 2 N_c - 1 and h_W placed circularly, the
+// circular convolution of length L equals the linear one on [0, N_c), so the
+// kernel computes it as IFFT(FFT(p) * H) with H = DFT_L(h_W) precomputed on
+// the host in FP64 (real and even, since h_W is symmetric).
+//
+// Two rows share one complex transform: z = p0 + i p1.  Because H is real,
+// IFFT(FFT(z) H) = q0 + i q1, so one forward and one inverse complex FFT
+// filter two rows with no real-FFT pre/post-processing.  The inverse is done
+// as conj(FFT(conj(Z H))) with the 1/(L pitch) folded into H.
+//
+// The whole transform lives in LDS (L <= 16384 complex FP32 = 128 KiB) and
+// runs as mixed-radix Stockham passes (radix 4, plus one radix-2 pass when
+// log2 L is odd); each pass reads its operands into registers, synchronises,
+// and writes the results in place.  Twiddles exp(-2 pi i e / L) come from a
+// table computed on the host in FP64.
+#include "xct_internal.h"
+
+namespace xct {
+
+template <typename T>
+__device__ __forceinline__ float ld_in(const T *p, int64_t i);
+template <>
+__device__ __forceinline__ float ld_in<float>(const float *p, int64_t i) { return p[i]; }
+template <>
+__device__ __forceinline__ float ld_in<f16_t>(const f16_t *p, int64_t i) { return (float)p[i]; }
+template <>
+__device__ __forceinline__ float ld_in<bf16_t>(const bf16_t *p, int64_t i)
+{
+    return __uint_as_float((uint32_t)p[i].bits << 16);
+}
+
+template <typename T>
+__device__ __forceinline__ void st_out(T *p, int64_t i, float v);
+template <>
+__device__ __forceinline__ void st_out<float>(float *p, int64_t i, float v) { p[i] = v; }
+template <>
+__device__ __forceinline__ void st_out<f16_t>(f16_t *p, int64_t i, float v) { p[i] = (f16_t)v; }
+template <>
+__device__ __forceinline__ void st_out<bf16_t>(bf16_t *p, int64_t i, float v)
+{
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7fffffffu) > 0x7f800000u) {
+        p[i].bits = (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+    } else {
+        u += 0x7fffu + ((u >> 16) & 1u);             // round to nearest even
+        p[i].bits = (uint16_t)(u >> 16);
+    }
+}
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// One radix-2 Stockham pass of span Ns (only as the first pass, Ns = 1).
+__device__ __forceinline__ void pass_r2(float2 *z, int L, int Ns, const float2 *tw, int tid, int nt)
+{
+    float2 v0[8], v1[8];
+    const int half = L >> 1;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int j = tid + q * nt;
+        if (j < half) {
+            v0[q] = z[j];
+            v1[q] = z[j + half];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int j = tid + q * nt;
+        if (j < half) {
+            const int k = j & (Ns - 1);
+            const float2 b = (Ns > 1) ? cmul(v1[q], tw[k * (L / (2 * Ns))]) : v1[q];
+            const int base = ((j - k) << 1) + k;
+            z[base] = make_float2(v0[q].x + b.x, v0[q].y + b.y);
+            z[base + Ns] = make_float2(v0[q].x - b.x, v0[q].y - b.y);
+        }
+    }
+    __syncthreads();
+}
+
+// One radix-4 Stockham pass of span Ns.
+__device__ __forceinline__ void pass_r4(float2 *z, int L, int Ns, const float2 *tw, int tid, int nt)
+{
+    float2 v[4][4];
+    const int quarter = L >> 2;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = tid + q * nt;
+        if (j < quarter) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[q][r] = z[j + r * quarter];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = tid + q * nt;
+        if (j < quarter) {
+            const int k = j & (Ns - 1);
+            float2 x0 = v[q][0], x1 = v[q][1], x2 = v[q][2], x3 = v[q][3];
+            if (Ns > 1) {
+                const int e1 = k * (quarter / Ns);
+                x1 = cmul(x1, tw[e1]);
+                x2 = cmul(x2, tw[2 * e1]);
+                x3 = cmul(x3, tw[3 * e1]);
+            }
+            const float2 a0 = make_float2(x0.x + x2.x, x0.y + x2.y);
+            const float2 a1 = make_float2(x0.x - x2.x, x0.y - x2.y);
+            const float2 a2 = make_float2(x1.x + x3.x, x1.y + x3.y);
+            const float2 a3 = make_float2(x1.y - x3.y, x3.x - x1.x);  // -i (x1 - x3)
+            const int base = ((j - k) << 2) + k;
+            z[base] = make_float2(a0.x + a2.x, a0.y + a2.y);
+            z[base + Ns] = make_float2(a1.x + a3.x, a1.y + a3.y);
+            z[base + 2 * Ns] = make_float2(a0.x - a2.x, a0.y - a2.y);
+            z[base + 3 * Ns] = make_float2(a1.x - a3.x, a1.y - a3.y);
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void fft_forward(float2 *z, int L, int log2L, const float2 *tw, int tid,
+                                            int nt)
+{
+    int Ns = 1;
+    if (log2L & 1) {
+        pass_r2(z, L, 1, tw, tid, nt);
+        Ns = 2;
+    }
+    for (; Ns < L; Ns <<= 2) pass_r4(z, L, Ns, tw, tid, nt);
+}
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(1024) void filter_kernel(FilterArgs a)
+{
+    extern __shared__ float2 z[];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int L = a.L, nc = a.nc;
+    const int64_t r0 = (int64_t)blockIdx.x * 2;
+    const bool has1 = r0 + 1 < a.rows;
+    const TI *p0 = static_cast<const TI *>(a.in) + r0 * nc;
+    const TI *p1 = p0 + nc;
+
+    for (int n = tid; n < L; n += nt) {
+        float x0 = 0.0f, x1 = 0.0f;
+        if (n < nc) {
+            x0 = ld_in(p0, n);
+            if (has1) x1 = ld_in(p1, n);
+        }
+        z[n] = make_float2(x0, x1);
+    }
+    __syncthreads();
+    fft_forward(z, L, a.log2L, a.tw, tid, nt);
+    for (int n = tid; n < L; n += nt) {
+        const float h = a.H[n];
+        const float2 v = z[n];
+        z[n] = make_float2(v.x * h, -v.y * h);
+    }
+    __syncthreads();
+    fft_forward(z, L, a.log2L, a.tw, tid, nt);
+
+    TO *o0 = static_cast<TO *>(a.out) + r0 * nc;
+    TO *o1 = o0 + nc;
+    for (int n = tid; n < nc; n += nt) {
+        const float2 v = z[n];
+        st_out(o0, n, v.x);
+        if (has1) st_out(o1, n, -v.y);
+    }
+}
+
+template <typename TI, typename TO>
+static hipError_t launch_typed(const FilterArgs &a, hipStream_t s)
+{
+    const int nt = max(64, min(1024, a.L / 16));
+    const size_t lds = (size_t)a.L * sizeof(float2);
+    (void)hipGetLastError();  // report only what this launch does
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(filter_kernel<TI, TO>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    const int64_t pairs = (a.rows + 1) / 2;
+    hipLaunchKernelGGL((filter_kernel<TI, TO>), dim3((unsigned)pairs), dim3(nt), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename TI>
+static hipError_t launch_out(const FilterArgs &a, int out_t, hipStream_t s)
+{
+    if (out_t == XCT_F32) return launch_typed<TI, float>(a, s);
+    if (out_t == XCT_F16) return launch_typed<TI, f16_t>(a, s);
+    return launch_typed<TI, bf16_t>(a, s);
+}
+
+hipError_t launch_filter(const FilterArgs &a, int in_t, int out_t, hipStream_t s)
+{
+    if (in_t == XCT_F32) return launch_out<float>(a, out_t, s);
+    if (in_t == XCT_F16) return launch_out<f16_t>(a, out_t, s);
+    return launch_out<bf16_t>(a, out_t, s);
+}
+
+}  // namespace xct

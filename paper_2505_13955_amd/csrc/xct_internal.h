@@ -1,0 +1,81 @@
+// Internal declarations shared by the HIP sources of libxct.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/xct.h"
+
+namespace xct {
+
+constexpr int kMaxSlabs = 16;
+constexpr int kTile = 64;          // back-projection tile edge (pixels)
+constexpr int kBPThreads = 256;    // back-projection workgroup size
+constexpr int kMaxFFT = 16384;     // largest filter FFT length (LDS resident)
+
+// Storage types of sinogram elements.
+struct bf16_t { uint16_t bits; };
+typedef _Float16 f16_t;
+
+// One slab of slices as seen by the back-projection kernels.
+struct BPSlab {
+    const void *sino;    // [S][Np][Nc] filtered rows (dtype of the launch)
+    float *image;        // [S][Ny][Nx]
+    const float2 *cs;    // [Np] (cos, sin) * pixel / pitch, FP32
+    const double2 *csd;  // [Np] the same in FP64 (window anchors)
+    double center;       // c, in bins
+    int64_t item_begin;  // first work item of this slab
+    int32_t n_angles, n_det, nx, ny;
+    int32_t n_slices;
+    int32_t tiles_x, tiles_y;  // tiles per slice (symmetric path: of one quadrant)
+    int32_t mirror;            // 2c, an integer on the symmetric path
+    float scale;
+    int32_t accumulate;
+};
+
+struct BPBatch {
+    BPSlab slab[kMaxSlabs];
+    int64_t total_items;
+    unsigned int *counter;  // persistent work counter, or nullptr (one item per block)
+    int32_t n_slabs;
+    int32_t win;            // window entries per angle (per group on the symmetric path)
+    int32_t kb;             // angles (generic) / angle pairs (symmetric) per LDS stage
+    int32_t xcd_remap;      // map consecutive items to one XCD (non-persistent launches)
+};
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_bp_generic(const BPBatch &b, int dtype, int grid, size_t lds, hipStream_t s);
+hipError_t launch_bp_sym(const BPBatch &b, int dtype, int grid, size_t lds, hipStream_t s);
+size_t bp_generic_lds_bytes(int win, int kb);
+size_t bp_sym_lds_bytes(int win, int kb);
+int bp_max_blocks_per_cu(bool sym, int dtype, size_t lds);
+
+struct FilterArgs {
+    const void *in;    // [rows][Nc]
+    void *out;         // [rows][Nc]
+    const float2 *tw;  // [L] exp(-2 pi i e / L)
+    const float *H;    // [L] real spectrum / (L * pitch)
+    int64_t rows;
+    int32_t nc;
+    int32_t L;
+    int32_t log2L;
+};
+hipError_t launch_filter(const FilterArgs &a, int in_t, int out_t, hipStream_t s);
+
+struct FPArgs {
+    const float *image;  // [S][Ny][Nx]
+    float *sino;         // [S][Np][Nc]
+    const double2 *csd;  // [Np] (cos, sin) * pixel / pitch
+    double center;
+    float scale;         // pixel^2 / pitch
+    int32_t n_angles, n_det, nx, ny, n_slices;
+};
+hipError_t launch_forward(const FPArgs &a, hipStream_t s);
+
+hipError_t launch_reduce(const float *a, const float *b, int64_t n, double *result,
+                         double *partials, int nblocks, int sqdist, hipStream_t s);
+int reduce_blocks(int64_t n);
+
+hipError_t launch_fill_u32(unsigned int *p, int n, unsigned int v, hipStream_t s);
+
+}  // namespace xct

@@ -1,0 +1,143 @@
+"""The C ABI without a GPU: the library loads, exports every entry point the
+header declares, and rejects bad arguments with the documented status codes
+before it makes any HIP call (so these run on a machine with no GPU)."""
+
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2505_13955_amd as pkg
+from paper_2505_13955_amd import xct as X
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+EINVAL, EDTYPE, EWORKSPACE, ETOOBIG = -1, -2, -3, -4
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "xct.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(xct_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return pkg.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = header_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(X.EXPORTS) == names
+
+
+def test_version_and_status_strings(lib):
+    assert lib.xct_version() == 10000
+    assert lib.xct_status_string(0) == b"ok"
+    for code in (-1, -2, -3, -4, -5):
+        assert lib.xct_status_string(code) not in (b"ok", b"unknown status")
+    assert lib.xct_last_hip_error() == 0
+
+
+def _geom(**kw):
+    base = dict(n_angles=8, n_det=16, nx=8, ny=8, det_pitch=1.0, pixel_size=1.0, center=7.5,
+                angles=np.linspace(0, math.pi, 8, endpoint=False))
+    base.update(kw)
+    ang = np.ascontiguousarray(base.pop("angles"), dtype=np.float64)
+    g = X.XctGeometry(base["n_angles"], base["n_det"], base["nx"], base["ny"], base["det_pitch"],
+                      base["pixel_size"], base["center"],
+                      ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return g, ang
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n_angles=0), EINVAL), (dict(n_det=-1), EINVAL), (dict(nx=0), EINVAL),
+    (dict(det_pitch=0.0), EINVAL), (dict(pixel_size=-1.0), EINVAL),
+    (dict(center=float("nan")), EINVAL), (dict(det_pitch=float("inf")), EINVAL),
+    (dict(n_det=70000), ETOOBIG), (dict(pixel_size=100.0), ETOOBIG),
+    (dict(pixel_size=0.01), ETOOBIG), (dict(center=1e7), ETOOBIG),
+])
+def test_geometry_validation(lib, kw, code):
+    g, ang = _geom(**kw)
+    assert lib.xct_backproject(ctypes.byref(g), 1, FAKE, 0, FAKE, 1.0, 0, None) == code
+    assert lib.xct_forward_project(ctypes.byref(g), 1, FAKE, FAKE, None) == code
+
+
+def test_angle_validation(lib):
+    ang = np.linspace(0, 1, 8)
+    ang[3] = np.nan
+    g, keep = _geom(angles=ang)
+    assert lib.xct_backproject(ctypes.byref(g), 1, FAKE, 0, FAKE, 1.0, 0, None) == EINVAL
+    g2 = X.XctGeometry(8, 16, 8, 8, 1.0, 1.0, 7.5, None)
+    assert lib.xct_backproject(ctypes.byref(g2), 1, FAKE, 0, FAKE, 1.0, 0, None) == EINVAL
+
+
+def test_filter_validation(lib):
+    g, ang = _geom()
+    assert lib.xct_filter(ctypes.byref(g), 0, FAKE, 0, FAKE, 0, 0, None) == EINVAL
+    assert lib.xct_filter(ctypes.byref(g), 1, None, 0, FAKE, 0, 0, None) == EINVAL
+    assert lib.xct_filter(ctypes.byref(g), 1, FAKE, 3, FAKE, 0, 0, None) == EDTYPE
+    assert lib.xct_filter(ctypes.byref(g), 1, FAKE, 0, FAKE, 0, 3, None) == EDTYPE
+    assert lib.xct_filter(ctypes.byref(g), 1, FAKE, 1, FAKE, 0, 0, None) == EINVAL  # in place, dtype change
+    big, ang2 = _geom(n_det=8193)
+    assert lib.xct_filter(ctypes.byref(big), 1, FAKE, 0, ctypes.c_void_p(0x2000), 0, 0, None) == ETOOBIG
+    huge, ang3 = _geom(n_angles=1 << 20, angles=np.zeros(1 << 20), n_det=1 << 16)
+    assert lib.xct_filter(ctypes.byref(huge), 1 << 30, FAKE, 0, FAKE, 0, 0, None) == ETOOBIG
+
+
+def test_backproject_validation(lib):
+    g, ang = _geom()
+    assert lib.xct_backproject(ctypes.byref(g), 1, FAKE, 0, FAKE, float("nan"), 0, None) == EINVAL
+    assert lib.xct_backproject(ctypes.byref(g), 1, FAKE, 7, FAKE, 1.0, 0, None) == EDTYPE
+    assert lib.xct_backproject(None, 1, FAKE, 0, FAKE, 1.0, 0, None) == EINVAL
+    assert lib.xct_forward_project(ctypes.byref(g), 70000, FAKE, FAKE, None) == ETOOBIG
+
+
+def test_fbp_batch_validation(lib):
+    g, ang = _geom()
+    slabs = (X.XctSlab * 2)()
+    for s in slabs:
+        s.geom = g
+        s.n_slices = 2
+        s.sino = FAKE
+        s.image = FAKE
+    need = lib.xct_fbp_workspace_bytes(slabs, 2, 0)
+    assert need == 256 + 2 * 1024  # two slabs of 2*8*16 FP32 values, 256-aligned
+    assert lib.xct_fbp_workspace_bytes(slabs, 2, 1) == 256 + 2 * 512
+    assert lib.xct_fbp_workspace_bytes(slabs, 0, 0) == 0
+    ws = ctypes.c_void_p(0x10000)
+    assert lib.xct_fbp_batch(slabs, 2, 0, 0, 0, ws, need - 1, None) == EWORKSPACE
+    assert lib.xct_fbp_batch(slabs, 2, 0, 0, 0, ctypes.c_void_p(0x10010), need, None) == EWORKSPACE
+    assert lib.xct_fbp_batch(slabs, 2, 0, 0, 0, None, need, None) == EWORKSPACE
+    assert lib.xct_fbp_batch(slabs, 2, 0, 9, 0, ws, need, None) == EDTYPE
+    assert lib.xct_fbp_batch(slabs, 17, 0, 0, 0, ws, need, None) == ETOOBIG
+    slabs[1].image = None
+    assert lib.xct_fbp_batch(slabs, 2, 0, 0, 0, ws, need, None) == EINVAL
+
+
+def test_reduce_validation(lib):
+    assert lib.xct_reduce_workspace_bytes(0) == 0
+    assert lib.xct_reduce_workspace_bytes(10) == 8
+    assert lib.xct_reduce_workspace_bytes(10**9) == 8 * 1024
+    assert lib.xct_dot_f64(FAKE, FAKE, 0, FAKE, FAKE, 8, None) == EINVAL
+    assert lib.xct_dot_f64(FAKE, FAKE, 100, FAKE, FAKE, 0, None) == EWORKSPACE
+    assert lib.xct_sqdist_f64(FAKE, FAKE, 100, FAKE, ctypes.c_void_p(0x1004), 8, None) == EWORKSPACE
+
+
+def test_binding_rejects_host_tensors():
+    import torch
+
+    g, ang = _geom()
+
+    class G:
+        n_angles, n_det, nx, ny, det_pitch, pixel_size, center = 8, 16, 8, 8, 1.0, 1.0, 7.5
+        angles = np.zeros(8)
+
+    with pytest.raises(ValueError):
+        pkg.xct_backproject(G, torch.zeros(1, 8, 16), torch.zeros(1, 8, 8), 1.0)

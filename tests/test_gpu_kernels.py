@@ -1,0 +1,297 @@
+"""GPU parity of each kernel against the FP64 oracle at sizes the oracle runs in
+seconds: several 64x64 tiles plus ragged tails, odd and even sizes, every
+window and storage type, both back-projection paths, the forward projector,
+the FP64 reductions, and the degenerate cases (one angle, one bin, one pixel)."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from synth import configs
+from tests.gpu_util import rel_l2, say, sample_pixels, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 1e-4  # relative L2 vs the FP64 oracle, FP32 path
+
+
+@pytest.fixture(scope="module")
+def xct():
+    import paper_2505_13955_amd as pkg
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    pkg.load_library()
+    return pkg
+
+
+def _geom(**kw):
+    return synth.Geometry(**kw)
+
+
+# ---------------------------------------------------------------- filter
+@pytest.mark.parametrize("window", ["ram_lak", "shepp_logan", "hann"])
+@pytest.mark.parametrize("nc", [1, 2, 7, 64, 367, 1000, 2900, 8192])
+def test_filter_matches_oracle(xct, window, nc):
+    rng = np.random.default_rng(nc)
+    rows = 5 if nc >= 2900 else 9  # odd: one unpaired row
+    p = rng.standard_normal((1, rows, nc)) * 3 + 1
+    g = _geom(n_angles=rows, n_det=nc, nx=4, ny=4, det_pitch=0.75)
+    say("filter", window, nc)
+    q = xct.filter(to_dev(p), g, window)
+    torch.cuda.synchronize()
+    ref = oracle.filter(p, 0.75, window)
+    err = rel_l2(q.cpu().numpy(), ref)
+    assert err < 5e-6, err
+
+
+@pytest.mark.parametrize("sin_t,sout_t", [(torch.float16, torch.float32), (torch.bfloat16, torch.float32),
+                                          (torch.float32, torch.float16), (torch.float32, torch.bfloat16),
+                                          (torch.bfloat16, torch.bfloat16)])
+def test_filter_storage_types(xct, sin_t, sout_t):
+    rng = np.random.default_rng(5)
+    p = torch.as_tensor(rng.standard_normal((2, 7, 300)) * 10)
+    stored = p.to(torch.float32).to(sin_t)
+    g = _geom(n_angles=7, n_det=300, nx=4, ny=4)
+    say("filter storage", sin_t, sout_t)
+    q = xct.filter(stored.to("cuda").contiguous(), g, "hann", out_dtype=sout_t)
+    torch.cuda.synchronize()
+    ref = oracle.filter(stored.to(torch.float64).numpy(), 1.0, "hann")
+    got = q.to(torch.float64).cpu().numpy()
+    tol = 5e-6 if sout_t == torch.float32 else (1e-3 if sout_t == torch.float16 else 8e-3)
+    assert rel_l2(got, ref) < tol
+    if sout_t != torch.float32:
+        # output is the FP32 result rounded to the storage type
+        q32 = xct.filter(stored.to("cuda").contiguous(), g, "hann")
+        assert torch.equal(q32.to(sout_t), q)
+
+
+def test_filter_in_place(xct):
+    rng = np.random.default_rng(6)
+    p = rng.standard_normal((1, 8, 100))
+    g = _geom(n_angles=8, n_det=100, nx=4, ny=4)
+    t = to_dev(p)
+    xct.xct_filter(g, t, t, "shepp_logan")
+    torch.cuda.synchronize()
+    assert rel_l2(t.cpu().numpy(), oracle.filter(p, 1.0, "shepp_logan")) < 5e-6
+
+
+# ---------------------------------------------------------------- back-projection
+BP_CASES = [
+    # (nx, ny, n_angles, n_det, pitch, pixel, center, angles) -> exercises the generic path
+    dict(nx=130, ny=70, n_angles=45, n_det=181, det_pitch=1.0, pixel_size=1.0, center=88.3, angles="rand"),
+    dict(nx=64, ny=64, n_angles=33, n_det=97, det_pitch=0.8, pixel_size=1.1, center=47.0, angles="rand"),
+    dict(nx=1, ny=1, n_angles=3, n_det=5, det_pitch=1.0, pixel_size=1.0, center=2.0, angles="rand"),
+    dict(nx=200, ny=3, n_angles=7, n_det=50, det_pitch=2.0, pixel_size=0.5, center=24.5, angles="rand"),
+    dict(nx=97, ny=97, n_angles=1, n_det=1, det_pitch=1.0, pixel_size=1.0, center=0.0, angles="rand"),
+    # symmetric path: square, even, angle set closed under +pi/2, 2c integral
+    dict(nx=256, ny=256, n_angles=360, n_det=367, det_pitch=1.0, pixel_size=1.0, center=183.0, angles="uni"),
+    dict(nx=100, ny=100, n_angles=60, n_det=143, det_pitch=1.0, pixel_size=1.0, center=71.0, angles="uni"),
+    dict(nx=130, ny=130, n_angles=2, n_det=186, det_pitch=1.0, pixel_size=1.0, center=92.5, angles="uni"),
+    dict(nx=2, ny=2, n_angles=4, n_det=3, det_pitch=1.0, pixel_size=1.0, center=1.0, angles="uni"),
+    dict(nx=192, ny=192, n_angles=48, n_det=150, det_pitch=1.3, pixel_size=0.9, center=74.5, angles="uni"),
+    dict(nx=128, ny=128, n_angles=36, n_det=100, det_pitch=1.0, pixel_size=1.0, center=40.0, angles="uni"),
+]
+
+
+def _case_geom(c, rng):
+    c = dict(c)
+    if c["angles"] == "rand":
+        c["angles"] = rng.uniform(-math.pi, 2 * math.pi, c["n_angles"])
+    else:
+        c["angles"] = synth.uniform_angles(c["n_angles"])
+    return _geom(**c)
+
+
+@pytest.mark.parametrize("case", range(len(BP_CASES)))
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float16, torch.bfloat16])
+def test_backproject_matches_oracle(xct, case, dtype):
+    rng = np.random.default_rng(100 + case)
+    g = _case_geom(BP_CASES[case], rng)
+    S = 2
+    q = rng.standard_normal((S, g.n_angles, g.n_det))
+    stored = torch.as_tensor(q).to(torch.float32).to(dtype)
+    say("bp", case, dtype, g.nx, g.ny, g.n_angles, g.n_det)
+    img = xct.backproject(stored.to("cuda").contiguous(), g, scale=0.37)
+    torch.cuda.synchronize()
+    ref = oracle.backproject(stored.to(torch.float64).numpy(), g, 0.37)
+    err = rel_l2(img.cpu().numpy(), ref)
+    assert err < 2e-5, err
+
+
+def test_backproject_accumulate_and_scale(xct):
+    rng = np.random.default_rng(9)
+    g = _geom(n_angles=40, n_det=90, nx=64, ny=64)
+    q = rng.standard_normal((1, 40, 90))
+    base = rng.standard_normal((1, 64, 64))
+    img = to_dev(base)
+    xct.xct_backproject(g, to_dev(q), img, -1.5, accumulate=True)
+    torch.cuda.synchronize()
+    ref = base - 1.5 * oracle.backproject(q.astype(np.float32).astype(np.float64), g)
+    assert rel_l2(img.cpu().numpy(), ref) < 2e-5
+
+
+def test_symmetric_and_generic_paths_agree(xct):
+    """The same uniform geometry through the symmetric path, and through the
+    generic path (angles nudged so the quarter-turn pairing no longer holds)."""
+    rng = np.random.default_rng(10)
+    g = _geom(n_angles=90, n_det=181, nx=128, ny=128)
+    ang = g.angles.copy()
+    ang[-1] += 1e-7
+    g2 = g.replace(angles=ang)
+    q = to_dev(rng.standard_normal((1, 90, 181)))
+    a = xct.backproject(q, g)
+    b = xct.backproject(q, g2)
+    torch.cuda.synchronize()
+    assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) < 2e-5
+
+
+def test_backproject_is_deterministic(xct):
+    rng = np.random.default_rng(11)
+    for g in (_geom(n_angles=128, n_det=300, nx=200, ny=200),
+              _geom(n_angles=61, n_det=300, nx=150, ny=170, center=140.2)):
+        q = to_dev(rng.standard_normal((2, g.n_angles, 300)))
+        a = xct.backproject(q, g)
+        b = xct.backproject(q, g)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+
+
+# ---------------------------------------------------------------- forward projector
+FP_CASES = [
+    dict(nx=64, ny=64, n_angles=37, n_det=97, det_pitch=1.0, pixel_size=1.0, center=48.0),
+    dict(nx=90, ny=50, n_angles=23, n_det=120, det_pitch=0.7, pixel_size=1.2, center=61.3),
+    dict(nx=1, ny=1, n_angles=5, n_det=3, det_pitch=1.0, pixel_size=1.0, center=1.0),
+    dict(nx=33, ny=129, n_angles=16, n_det=200, det_pitch=1.5, pixel_size=1.0, center=99.5),
+]
+
+
+@pytest.mark.parametrize("case", range(len(FP_CASES)))
+def test_forward_matches_oracle(xct, case):
+    rng = np.random.default_rng(200 + case)
+    c = dict(FP_CASES[case])
+    c["angles"] = rng.uniform(0, 2 * math.pi, c["n_angles"])
+    c["angles"][:4] = [0.0, math.pi / 2, math.pi / 4, math.pi][: len(c["angles"][:4])]
+    g = _geom(**c)
+    x = rng.standard_normal((2, g.ny, g.nx))
+    say("fp", case)
+    y = xct.forward_project(to_dev(x), g)
+    torch.cuda.synchronize()
+    ref = oracle.forward(x.astype(np.float32).astype(np.float64), g)
+    assert rel_l2(y.cpu().numpy(), ref) < 2e-5
+
+
+def test_adjoint_identity_fp64(xct):
+    rng = np.random.default_rng(12)
+    g = _geom(n_angles=50, n_det=150, nx=100, ny=100, det_pitch=1.1, pixel_size=0.9, center=74.2,
+              angles=rng.uniform(0, math.pi, 50))
+    x = to_dev(rng.standard_normal((2, 100, 100)))
+    y = to_dev(rng.standard_normal((2, 50, 150)))
+    Px = xct.forward_project(x, g)
+    PTy = xct.backproject(y, g, xct.adjoint_scale(g))
+    lhs = float(xct.xct_dot_f64(Px, y))
+    rhs = float(xct.xct_dot_f64(x, PTy))
+    nrm = float(torch.linalg.norm(Px.double())) * float(torch.linalg.norm(y.double()))
+    assert abs(lhs - rhs) / nrm < 1e-5
+
+
+# ---------------------------------------------------------------- reductions
+@pytest.mark.parametrize("n", [1, 255, 256 * 8 + 3, 1_000_003])
+def test_fp64_reductions(xct, n):
+    rng = np.random.default_rng(n)
+    a = rng.standard_normal(n).astype(np.float32)
+    b = rng.standard_normal(n).astype(np.float32)
+    da, db = to_dev(a), to_dev(b)
+    dot = float(xct.xct_dot_f64(da, db))
+    sq = float(xct.xct_sqdist_f64(da, db))
+    a64, b64 = a.astype(np.float64), b.astype(np.float64)
+    assert abs(dot - np.dot(a64, b64)) <= 1e-12 * np.abs(a64 * b64).sum()
+    assert abs(sq - np.sum((a64 - b64) ** 2)) <= 1e-12 * np.sum((a64 - b64) ** 2)
+    assert float(xct.xct_dot_f64(da, db)) == dot  # reproducible
+
+
+# ---------------------------------------------------------------- FBP
+def test_fbp_c1_full_slice(xct):
+    """The 256^2 / 360-angle / 367-bin / centre-183 Ram-Lak slice, whole image."""
+    spec = configs.c1()
+    p = spec.slab()
+    say("fbp c1")
+    img = xct.fbp(p.to(torch.float32).to("cuda"), spec.geom, spec.window)
+    torch.cuda.synchronize()
+    ref = oracle.fbp(p.to(torch.float32).to(torch.float64).numpy(), spec.geom, spec.window)
+    err = rel_l2(img.cpu().numpy(), ref)
+    say("fbp c1 rel L2", err)
+    assert err < TOL_F32
+
+
+def test_fbp_c1_golden_samples(xct):
+    import json
+    import os
+
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c1_oracle_fbp.json")) as f:
+        gold = json.load(f)
+    spec = configs.c1()
+    img = xct.fbp(spec.slab().to(torch.float32).to("cuda"), spec.geom, spec.window)
+    pix = np.array(gold["pixels"])
+    got = img.cpu().numpy()[pix[:, 0], pix[:, 1], pix[:, 2]]
+    # the stored oracle values used the FP64 sinogram; FP32 input rounding is ~1e-7
+    assert rel_l2(got, gold["values"]) < TOL_F32
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("fdt", [torch.float32, torch.float16])
+def test_fbp_small_slabs_storage(xct, storage, fdt):
+    """Shrunk versions of the slab recipes, every storage type, FP32 or FP16
+    filtered rows; the oracle sees the decoded stored sinogram."""
+    for name, spec in (("c2", configs.shrink(configs.c2(), 160, 120, 3)),
+                       ("c3", configs.shrink(configs.c3(), 192, 144, 2))):
+        p = spec.slab()
+        stored = synth.encode_storage(p, storage)
+        say("fbp small", name, storage, fdt)
+        img = xct.fbp(stored.to("cuda"), spec.geom, spec.window, filtered_dtype=fdt)
+        torch.cuda.synchronize()
+        ref = oracle.fbp(synth.decode_storage(stored).numpy(), spec.geom, spec.window)
+        err = rel_l2(img.cpu().numpy(), ref)
+        say("  rel L2", err)
+        tol = TOL_F32 if (storage == "f32" and fdt == torch.float32) else 2e-3
+        assert err < tol, (name, storage, fdt, err)
+
+
+def test_fbp_batch_uneven_small(xct):
+    """Three slabs of different sizes (the uneven-batch recipe at 1/8 scale) in
+    one persistent launch, BF16 storage."""
+    specs = configs.c5(scale=8)
+    slabs, refs = [], []
+    for spec in specs:
+        p = synth.encode_storage(spec.slab(), "bf16")
+        img = torch.empty((spec.n_slices, spec.geom.ny, spec.geom.nx), device="cuda")
+        slabs.append((spec.geom, p.to("cuda"), img))
+        refs.append(oracle.fbp(synth.decode_storage(p).numpy(), spec.geom, spec.window))
+    say("fbp batch small")
+    xct.xct_fbp_batch(slabs, "ram_lak")
+    torch.cuda.synchronize()
+    for (g, _, img), ref in zip(slabs, refs):
+        err = rel_l2(img.cpu().numpy(), ref)
+        assert err < 2e-3, err
+
+
+def test_fbp_batch_mixed_paths(xct):
+    """One slab takes the symmetric kernel, one the generic kernel (odd size),
+    one a non-uniform angle set; all in a single call."""
+    rng = np.random.default_rng(13)
+    geoms = [_geom(n_angles=64, n_det=150, nx=100, ny=100),
+             _geom(n_angles=50, n_det=120, nx=81, ny=81),
+             _geom(n_angles=31, n_det=140, nx=90, ny=70, center=70.3,
+                   angles=np.sort(rng.uniform(0, math.pi, 31)))]
+    slabs, refs = [], []
+    for g in geoms:
+        p = rng.standard_normal((2, g.n_angles, g.n_det))
+        slabs.append((g, to_dev(p), torch.empty((2, g.ny, g.nx), device="cuda")))
+        refs.append(oracle.fbp(p.astype(np.float32).astype(np.float64), g, "shepp_logan"))
+    xct.xct_fbp_batch(slabs, "shepp_logan")
+    torch.cuda.synchronize()
+    for (g, _, img), ref in zip(slabs, refs):
+        assert rel_l2(img.cpu().numpy(), ref) < TOL_F32
