@@ -1,0 +1,219 @@
+"""Throughput of per-slice parallel-beam filtered back-projection on one MI355X.
+
+One step is the whole hot path over one slab: the windowed ramp filter of every
+sinogram row (xct_filter) followed by the back-projection of every filtered row
+into its slice (xct_backproject, weight pi/N_p).  The workload is the paper's
+resolution: 16 slices of 8192^2, 6144 angles over a half turn, 8192 detector
+bins, Hann window, seeded binder discs holding 200 aggregate / void ellipses
+(closed-form line integrals, generated on the GPU before timing).  Inputs are
+resident in HBM when the timed region starts.
+
+value = voxel x angle updates per second (16 * 8192^2 * 6144 per step) / 1e9,
+for the FP32-stored sinogram; the FP16- and BF16-stored runs (FP32 arithmetic)
+are reported beside it, each with its relative L2 error against the FP64 oracle
+on a sample of pixels.
+
+    python bench.py [--steps K] [--warmup W] [--slices S] [--no-oracle]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "GUPS (voxel×angle updates/s) for FBP, fp32 vs fp16-storage, at stated L2 error"
+FLOPS_PER_UPDATE = 6  # coordinate FMA (2), fraction (1), interpolation FMA (2), accumulate (1)
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBPS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--slices", type=int, default=16, help="slices in the slab (16 = full workload)")
+    ap.add_argument("--storage", default="f32,f16,bf16")
+    ap.add_argument("--filtered", default="f32", choices=["f32", "f16"],
+                    help="storage of the filtered rows between the two kernels")
+    ap.add_argument("--no-oracle", action="store_true", help="skip the error and CPU-baseline legs")
+    ap.add_argument("--sample-rows", type=int, default=32,
+                    help="rows of one slice checked against / timed on the FP64 oracle")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the slab path shards "
+              "by slices with no exchange, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2505_13955_amd as xct
+    from synth import configs, decode_storage, encode_storage
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    spec = configs.c3(n_slices=args.slices)
+    g = spec.geom
+    S = spec.n_slices
+    updates = S * g.nx * g.ny * g.n_angles
+
+    t0 = time.time()
+    p64 = torch.empty((S, g.n_angles, g.n_det), dtype=torch.float64, device=dev)
+    for s in range(S):
+        p64[s] = spec.sinogram(s, device=dev)
+    torch.cuda.synchronize()
+    log(f"generated {S} sinograms in {time.time() - t0:.1f}s")
+
+    storages = [s for s in args.storage.split(",") if s]
+    fdt = torch.float32 if args.filtered == "f32" else torch.float16
+    filt = torch.empty((S, g.n_angles, g.n_det), dtype=fdt, device=dev)
+    image = torch.empty((S, g.ny, g.nx), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    w = math.pi / g.n_angles
+
+    # oracle sample: one slice, every (N/sample_rows)-th row, all columns
+    samp_slice = S // 2
+    rows = np.linspace(0, g.ny - 1, args.sample_rows).round().astype(np.int64)
+    pix = np.stack([np.zeros(rows.size * g.nx, np.int64), np.repeat(rows, g.nx),
+                    np.tile(np.arange(g.nx, dtype=np.int64), rows.size)], 1)
+
+    results = {}
+    fp32_image_sample = None
+    cpu = None
+    ref64 = None
+    for st in storages:
+        sino = encode_storage(p64, st).contiguous()
+
+        def step():
+            xct.xct_filter(g, sino, filt, spec.window)
+            xct.xct_backproject(g, filt, image, w, False)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t_wall = time.time()
+        for k in range(args.steps):
+            ev[k][0].record(stream)
+            xct.xct_filter(g, sino, filt, spec.window)
+            ev[k][1].record(stream)
+            xct.xct_backproject(g, filt, image, w, False)
+            ev[k][2].record(stream)
+        torch.cuda.synchronize()
+        t_wall = time.time() - t_wall
+        f_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
+        b_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps
+        step_ms = ev[0][0].elapsed_time(ev[-1][2]) / args.steps
+        r = {
+            "gups": updates / (step_ms * 1e-3) / 1e9,
+            "ms_per_step": step_ms,
+            "filter_ms": f_ms,
+            "bp_ms": b_ms,
+            "bp_gups": updates / (b_ms * 1e-3) / 1e9,
+            "wall_ms_per_step": 1e3 * t_wall / args.steps,
+        }
+        log(st, json.dumps({k: round(v, 3) for k, v in r.items()}))
+        got = image[samp_slice].cpu().numpy()[rows, :].ravel().astype(np.float64)
+        if st == "f32":
+            fp32_image_sample = got
+        elif fp32_image_sample is not None:
+            r["rel_l2_vs_gpu_f32"] = float(np.linalg.norm(got - fp32_image_sample)
+                                            / np.linalg.norm(fp32_image_sample))
+        if not args.no_oracle:
+            import oracle
+
+            stored = decode_storage(sino[samp_slice]).cpu().numpy()
+            t1 = time.time()
+            q = oracle.filter(stored, g.det_pitch, spec.window)
+            t_filter = time.time() - t1
+            t1 = time.time()
+            ref = oracle.backproject_pixels(q, g, pix, oracle.fbp_weight(g))
+            t_bp = time.time() - t1
+            r["rel_l2_vs_oracle"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+            if st == "f32":
+                samp_updates = pix.shape[0] * g.n_angles
+                t_fbp = t_bp + t_filter * rows.size / g.ny
+                cpu = {
+                    "value": samp_updates / t_fbp / 1e9,
+                    "unit": "GUPS",
+                    "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+                    "kind": "oracle",
+                    "sample": (f"FP64 oracle on slice {samp_slice}: filter of all {g.n_angles} rows "
+                               f"({t_filter:.1f}s, prorated to the sampled rows) + back-projection of "
+                               f"{rows.size} rows x {g.nx} columns x {g.n_angles} angles "
+                               f"({t_bp:.1f}s)"),
+                }
+                ref64 = ref
+            elif ref64 is not None:
+                # the FP32-stored input is the unquantised line integrals to ~1e-7
+                r["rel_l2_vs_oracle_f32_input"] = float(np.linalg.norm(got - ref64)
+                                                        / np.linalg.norm(ref64))
+            log(st, "rel L2 vs oracle", r["rel_l2_vs_oracle"])
+        results[st] = r
+        del sino
+
+    main_st = "f32" if "f32" in results else storages[0]
+    m = results[main_st]
+    bp_s = m["bp_ms"] * 1e-3
+    achieved = FLOPS_PER_UPDATE * updates / bp_s / 1e12
+    out = {
+        "metric": METRIC,
+        "value": m["gups"],
+        "unit": "GUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": m["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if main_st == "f32" else f"{main_st}-storage/f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"slab of {S} slices at 8192x8192, 6144 angles over [0,pi), 8192 bins, "
+                         "Hann, binder disc + 200 aggregate/void ellipses; sinogram stored as "
+                         f"{main_st}, filtered rows {args.filtered}"),
+            "slices": S, "nx": g.nx, "ny": g.ny, "n_angles": g.n_angles, "n_det": g.n_det,
+            "window": spec.window, "updates_per_step": updates,
+        },
+        "rel_l2": m.get("rel_l2_vs_oracle"),
+        "filter_ms": m["filter_ms"],
+        "bp_ms": m["bp_ms"],
+        "storage": {k: v for k, v in results.items()},
+        "roofline": {
+            "kernel": "bp_sym_kernel<float>",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+            "traffic": None,
+            "flops_per_update": FLOPS_PER_UPDATE,
+            "updates_per_launch": updates,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

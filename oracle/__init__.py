@@ -7,7 +7,7 @@ code with the HIP path.
 The arithmetic lives in ``xct_oracle.c`` (plain double-precision loops, built
 into ``liboracle.so`` by ``oracle.build``); this module marshals numpy arrays
 and adds the one step that uses a library primitive: ``filter_fft``, the same
-linear convolution as ``filter_direct`` evaluated through numpy's FP64 FFT,
+linear convolution as ``filter_direct`` evaluated through scipy's FP64 FFT,
 for detector widths where the direct O(N_c^2) sum is too slow.
 
 Definitions (the paper describes FBP only in words, Section IV-B and Section
@@ -30,6 +30,7 @@ import math
 import os
 
 import numpy as np
+import scipy.fft
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
@@ -101,7 +102,7 @@ def filter_direct(p, det_pitch: float, window: str) -> np.ndarray:
 
 
 def filter_fft(p, det_pitch: float, window: str) -> np.ndarray:
-    """The same linear convolution as ``filter_direct``, through numpy's FP64
+    """The same linear convolution as ``filter_direct``, through scipy's FP64
     FFT: zero-pad each row to L >= 2 N_c - 1, place h_W circularly
     (h[d] at index d mod L), multiply spectra, invert, keep [0, N_c)."""
     p = _f64(p)
@@ -111,13 +112,15 @@ def filter_fft(p, det_pitch: float, window: str) -> np.ndarray:
     hc = np.zeros(L)
     d = np.arange(-(nc - 1), nc)
     hc[d % L] = h
-    H = np.fft.rfft(hc)
+    H = scipy.fft.rfft(hc) / det_pitch
     out = np.empty_like(p)
     flat_in = p.reshape(-1, nc)
     flat_out = out.reshape(-1, nc)
-    for b in range(0, flat_in.shape[0], 512):
-        P = np.fft.rfft(flat_in[b:b + 512], n=L, axis=-1)
-        flat_out[b:b + 512] = np.fft.irfft(P * H, n=L, axis=-1)[:, :nc] / det_pitch
+    workers = os.cpu_count() or 1
+    for b in range(0, flat_in.shape[0], 256):
+        P = scipy.fft.rfft(flat_in[b:b + 256], n=L, axis=-1, workers=workers)
+        P *= H
+        flat_out[b:b + 256] = scipy.fft.irfft(P, n=L, axis=-1, workers=workers)[:, :nc]
     return out
 
 

@@ -1,0 +1,231 @@
+"""GPU parity at the full sizes of the measured workloads, on pixels and voxels
+the FP64 oracle computes one by one:
+
+* the 16 x 8192^2 slab (6144 angles, 8192 bins, Hann) in the launch
+  configuration the benchmark times (xct_filter then xct_backproject), with
+  the sinogram stored as FP32, FP16 and BF16;
+* the 64 x 2048^2 slab (1800 angles, 2900 bins, Shepp-Logan, Poisson noise)
+  through xct_fbp_batch;
+* the uneven batch (24 x 512^2, 12 x 1024^2, 4 x 2048^2, BF16) in one
+  persistent launch, bitwise equal to per-slab launches;
+* the differentiable pair on 32 x 1024^2 (1440 angles, 1449 bins): central
+  finite differences on 64 voxels, the adjoint identity in FP64, and the
+  gradient against the oracle's.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from synth import configs
+from tests.gpu_util import rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 1e-4
+TOL_REDUCED = 2e-3
+
+
+@pytest.fixture(scope="module")
+def xct():
+    import paper_2505_13955_amd as pkg
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    pkg.load_library()
+    return pkg
+
+
+def _oracle_pixels(stored_slice, geom, window, pixels):
+    """FP64 oracle FBP of one decoded slice at (row, col) pixels."""
+    q = oracle.filter(synth.decode_storage(stored_slice.cpu()).numpy(), geom.det_pitch, window)
+    pix = np.concatenate([np.zeros((len(pixels), 1), np.int64), pixels], 1)
+    return oracle.backproject_pixels(q, geom, pix, oracle.fbp_weight(geom))
+
+
+def _pixel_sample(rng, ny, nx, n):
+    return np.stack([rng.integers(0, ny, n), rng.integers(0, nx, n)], 1).astype(np.int64)
+
+
+# ---------------------------------------------------------------- 16 x 8192^2
+@pytest.fixture(scope="module")
+def c3_lines(xct):
+    spec = configs.c3()
+    say("generating 16 x 6144 x 8192 line integrals")
+    p = torch.empty((16, 6144, 8192), dtype=torch.float64, device="cuda")
+    for s in range(16):
+        p[s] = spec.sinogram(s, device="cuda")
+    torch.cuda.synchronize()
+    yield spec, p
+    del p
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("storage,fdt", [("f32", torch.float32), ("f16", torch.float32),
+                                         ("bf16", torch.float32), ("f16", torch.float16)])
+def test_c3_slab_bench_configuration(xct, c3_lines, storage, fdt):
+    spec, p64 = c3_lines
+    g = spec.geom
+    sino = synth.encode_storage(p64, storage).contiguous()
+    filt = torch.empty(sino.shape, dtype=fdt, device="cuda")
+    img = torch.empty((16, 8192, 8192), dtype=torch.float32, device="cuda")
+    say("c3", storage, fdt)
+    xct.xct_filter(g, sino, filt, spec.window)
+    xct.xct_backproject(g, filt, img, math.pi / g.n_angles, False)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    errs = []
+    for s in (0, 11):
+        pix = _pixel_sample(rng, 8192, 8192, 3000)
+        ref = _oracle_pixels(sino[s], g, spec.window, pix)
+        got = img[s].cpu().numpy()[pix[:, 0], pix[:, 1]]
+        errs.append(rel_l2(got, ref))
+    say("  rel L2 per slice", errs)
+    tol = TOL_F32 if storage == "f32" and fdt == torch.float32 else TOL_REDUCED
+    assert max(errs) < tol, errs
+    assert torch.isfinite(img).all()
+    del sino, filt, img
+
+
+def test_c3_slab_is_deterministic(xct, c3_lines):
+    spec, p64 = c3_lines
+    g = spec.geom
+    sino = p64[:4].to(torch.float32).contiguous()
+    filt = torch.empty_like(sino)
+    outs = []
+    for _ in range(2):
+        img = torch.empty((4, 8192, 8192), dtype=torch.float32, device="cuda")
+        xct.xct_filter(g, sino, filt, spec.window)
+        xct.xct_backproject(g, filt, img, math.pi / g.n_angles, False)
+        outs.append(img)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1])
+
+
+# ---------------------------------------------------------------- 64 x 2048^2
+def test_c2_slab_fbp_batch(xct):
+    spec = configs.c2()
+    g = spec.geom
+    say("c2 generate")
+    p = torch.empty((64, g.n_angles, g.n_det), dtype=torch.float32, device="cuda")
+    for s in range(64):
+        p[s] = spec.sinogram(s, device="cuda").to(torch.float32)
+    img = torch.empty((64, 2048, 2048), dtype=torch.float32, device="cuda")
+    say("c2 fbp")
+    xct.xct_fbp_batch([(g, p, img)], spec.window)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(2)
+    for s in (0, 37, 63):
+        pix = _pixel_sample(rng, 2048, 2048, 2000)
+        ref = _oracle_pixels(p[s], g, spec.window, pix)
+        err = rel_l2(img[s].cpu().numpy()[pix[:, 0], pix[:, 1]], ref)
+        say("  slice", s, "rel L2", err)
+        assert err < TOL_F32
+
+
+# ---------------------------------------------------------------- uneven batch
+def test_c5_uneven_batch_one_launch(xct):
+    specs = configs.c5()
+    slabs, stored = [], []
+    for spec in specs:
+        g = spec.geom
+        say("c5 generate", spec.name)
+        p = torch.stack([spec.sinogram(s, device="cuda") for s in range(spec.n_slices)])
+        sb = synth.encode_storage(p, "bf16").contiguous()
+        stored.append(sb)
+        slabs.append((g, sb, torch.empty((spec.n_slices, g.ny, g.nx), device="cuda")))
+    say("c5 fbp batch")
+    xct.xct_fbp_batch(slabs, "ram_lak")
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    for spec, (g, sb, img) in zip(specs, slabs):
+        # the persistent multi-slab launch equals a launch per slab, bit for bit
+        alone = torch.empty_like(img)
+        xct.xct_fbp_batch([(g, sb, alone)], "ram_lak")
+        torch.cuda.synchronize()
+        assert torch.equal(alone, img), spec.name
+        s = spec.n_slices - 1
+        pix = _pixel_sample(rng, g.ny, g.nx, 1500)
+        ref = _oracle_pixels(sb[s], g, spec.window, pix)
+        err = rel_l2(img[s].cpu().numpy()[pix[:, 0], pix[:, 1]], ref)
+        say("  ", spec.name, "rel L2", err)
+        assert err < TOL_REDUCED
+
+
+# ---------------------------------------------------------------- differentiable pair
+@pytest.fixture(scope="module")
+def c4_problem(xct):
+    spec = configs.c4()
+    g = spec.geom
+    say("c4 generate")
+    y = torch.stack([spec.sinogram(s, device="cuda") for s in range(32)]).to(torch.float32)
+    truth = torch.stack([spec.truth(s, device="cuda", supersample=2) for s in range(32)])
+    gen = torch.Generator(device="cuda").manual_seed(4)
+    x = (truth + 0.05 * torch.randn(truth.shape, generator=gen, device="cuda",
+                                    dtype=torch.float64)).to(torch.float32)
+    return spec, g, x.contiguous(), y.contiguous()
+
+
+def test_c4_autograd_finite_differences(xct, c4_problem):
+    spec, g, x, y = c4_problem
+    xr = x.clone().requires_grad_(True)
+    say("c4 forward/backward")
+    Px = xct.project(xr, g)
+    loss = ((Px - y) ** 2).sum()
+    loss.backward()
+    grad = xr.grad.detach()
+    r = (Px.detach() - y)
+    rng = np.random.default_rng(44)
+    h = 1e-3
+    worst = 0.0
+    for _ in range(64):
+        s, i, j = int(rng.integers(0, 32)), int(rng.integers(0, 1024)), int(rng.integers(0, 1024))
+        e = torch.zeros((1, 1024, 1024), dtype=torch.float32, device="cuda")
+        e[0, i, j] = 1.0
+        a = xct.forward_project(e, g)[0].double()  # column j of P, from the GPU kernel
+        r64 = r[s].double()
+        fd = (torch.sum((r64 + h * a) ** 2) - torch.sum((r64 - h * a) ** 2)) / (2 * h)
+        gj = float(grad[s, i, j])
+        rel = abs(float(fd) - gj) / max(abs(float(fd)), 1e-3 * float(torch.linalg.norm(a)) * float(torch.linalg.norm(r64)))
+        worst = max(worst, rel)
+    say("  worst FD relative error", worst)
+    assert worst < 1e-3
+
+
+def test_c4_adjoint_identity_fp64(xct, c4_problem):
+    spec, g, x, y = c4_problem
+    Px = xct.forward_project(x, g)
+    PTy = xct.backproject(y, g, xct.adjoint_scale(g))
+    lhs = float(xct.xct_dot_f64(Px, y))
+    rhs = float(xct.xct_dot_f64(x, PTy))
+    nrm = math.sqrt(float(xct.xct_dot_f64(Px, Px))) * math.sqrt(float(xct.xct_dot_f64(y, y)))
+    mism = abs(lhs - rhs) / nrm
+    say("  adjoint mismatch", mism)
+    assert mism < 1e-5
+
+
+def test_c4_gradient_against_oracle(xct, c4_problem):
+    spec, g, x, y = c4_problem
+    s = 17
+    xs, ys = x[s:s + 1].contiguous(), y[s:s + 1].contiguous()
+    loss, grad = xct.ls_loss_and_grad(xs, ys, g)
+    xr = xs.clone().requires_grad_(True)
+    Px = xct.project(xr, g)
+    ((Px - ys) ** 2).sum().backward()
+    torch.cuda.synchronize()
+    x64 = xs.double().cpu().numpy()[0]
+    y64 = ys.double().cpu().numpy()[0]
+    say("c4 oracle gradient")
+    r = oracle.forward(x64, g) - y64
+    gref = 2.0 * oracle.backproject(r, g, oracle.adjoint_scale(g))
+    lref = float(np.sum(r * r))
+    rho = float(np.linalg.norm(oracle.forward(x64, g)) / np.linalg.norm(r))
+    tol = max(1e-4, 2 * rho * math.sqrt(g.nx) * 2.0 ** -24)
+    e_auto = rel_l2(xr.grad.cpu().numpy()[0], gref)
+    e_stream = rel_l2(grad.cpu().numpy()[0], gref)
+    say("  rho", rho, "tol", tol, "autograd", e_auto, "streamed", e_stream)
+    assert e_auto < tol and e_stream < tol
+    assert abs(float(loss) - lref) / lref < 1e-5
