@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--filtered", default="f32", choices=["f32", "f16"],
                     help="storage of the filtered rows between the two kernels")
     ap.add_argument("--no-oracle", action="store_true", help="skip the error and CPU-baseline legs")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device-to-device copy three times (a known "
+                         "traffic reference for hardware byte counters)")
     ap.add_argument("--sample-rows", type=int, default=32,
                     help="rows of one slice checked against / timed on the FP64 oracle")
     return ap.parse_args()
@@ -75,11 +78,21 @@ def main():
     S = spec.n_slices
     updates = S * g.nx * g.ny * g.n_angles
 
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x 1 GiB copies done")
+        del src, dst
+
     t0 = time.time()
     p64 = torch.empty((S, g.n_angles, g.n_det), dtype=torch.float64, device=dev)
     for s in range(S):
         p64[s] = spec.sinogram(s, device=dev)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        log(f"sinogram {s + 1}/{S}")
     log(f"generated {S} sinograms in {time.time() - t0:.1f}s")
 
     storages = [s for s in args.storage.split(",") if s]

@@ -245,6 +245,7 @@ int window_entries(double ratio) { return (int)std::ceil(63.0 * std::sqrt(2.0) *
 bool symmetric_ok(const xct_geometry *g)
 {
     if (g->nx != g->ny || (g->nx & 1) || (g->n_angles & 1)) return false;
+    if (!bp_sym_window(window_entries(g->pixel_size / g->det_pitch))) return false;
     const double m = 2.0 * g->center;
     if (std::fabs(m - std::nearbyint(m)) > 1e-9) return false;
     const int H = g->n_angles / 2;
@@ -277,7 +278,8 @@ int tiles_of(const BPJob &j, int *tx, int *ty)
 }
 
 constexpr size_t kGenericStageBytes = 32 * 1024;
-constexpr size_t kSymStageBytes = 36 * 1024;
+constexpr size_t kSymStageBytes = 37 * 1024;      // 6 angle pairs of FP32 windows
+constexpr size_t kSymHalfStageBytes = 37 * 1024;  // 12 angle pairs of FP16 windows
 
 // Launch one back-projection over jobs that all take the same kernel
 // (all symmetric or all generic).  counter != nullptr makes it persistent.
@@ -319,20 +321,23 @@ int launch_bp_jobs(std::vector<BPJob> jobs, int dtype, unsigned int *counter, hi
     if (items >= (int64_t)1 << 31) return XCT_ETOOBIG;
     b.n_slabs = (int32_t)jobs.size();
     b.total_items = items;
-    b.win = W;
     b.counter = counter;
     size_t lds;
     if (sym) {
-        b.kb = (int)std::max<size_t>(1, kSymStageBytes / (64 * (size_t)W + 24));
-        lds = bp_sym_lds_bytes(W, b.kb);
+        W = bp_sym_window(W);  // the caller only routes windows that fit here
+        const bool half = dtype == XCT_F16;
+        const size_t per_pair = (half ? 2 : 4) * (size_t)W * sizeof(float4) + 24;
+        b.kb = (int)std::max<size_t>(1, (half ? kSymHalfStageBytes : kSymStageBytes) / per_pair);
+        lds = bp_sym_lds_bytes(W, b.kb, half);
     } else {
         b.kb = (int)std::max<size_t>(1, std::min<size_t>(64, kGenericStageBytes / (8 * (size_t)W + 16)));
         lds = bp_generic_lds_bytes(W, b.kb);
     }
+    b.win = W;
     if (lds > 160 * 1024) return XCT_ETOOBIG;
     int grid;
     if (counter) {
-        const int per_cu = bp_max_blocks_per_cu(sym, dtype, lds);
+        const int per_cu = bp_max_blocks_per_cu(sym, dtype, W, lds);
         grid = (int)std::min<int64_t>(items, (int64_t)per_cu * device_cus());
         b.xcd_remap = 0;
     } else {

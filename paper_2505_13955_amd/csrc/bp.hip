@@ -8,8 +8,12 @@
 // Work decomposition.  A workgroup of 256 threads owns a 64 x 64 pixel tile
 // and walks all angles in LDS stages.  For each angle of a stage the part of
 // the row the tile can touch (a window of W ~ 63 sqrt(2) + 3 bins) is copied
-// into LDS once, pre-paired as (q[n], q[n+1] - q[n]) so that the inner loop
-// needs one 8-byte LDS read and one FMA per interpolation.  Each thread keeps
+// into LDS once, pre-paired so that the inner loop needs one 8-byte LDS read
+// and one FMA per interpolation: entry m of a window that starts at bin B
+// holds d = q[B+m+1] - q[B+m] and a = q[B+m] - m d, so that for the local
+// coordinate u = (detector coordinate) - B, in [m, m+1),
+//   q[B+m] (1 - t) + q[B+m+1] t  =  a + u d,   t = u - m,
+// and the fraction t never has to be formed.  Each thread keeps
 // 16 pixels (a 4 x 4 lattice with stride 16) in registers; a wavefront covers
 // an 8 x 8 pixel block, whose detector footprint spans at most 12 bins, so its
 // LDS reads hit distinct banks or broadcast.
@@ -27,9 +31,12 @@
 //    Then the detector coordinate of pixel Q at th_k also gives, through the
 //    quarter-turn rotation R(x, y) = (y, -x) and the mirror u -> 2c - u of
 //    the detector, the coordinates of R^2 Q at th_k and of R^3 Q and R Q at
-//    th_k + pi/2.  One coordinate, floor and fraction then serve four updates,
-//    read from four windows interleaved in LDS (two 16-byte reads).  The
-//    workgroup owns a tile of the top-left quadrant and its three rotations.
+//    th_k + pi/2.  One coordinate and one floor then serve four updates,
+//    read from four windows that share one local coordinate.  The workgroup
+//    owns a tile of the top-left quadrant and its three rotations.  When the
+//    filtered rows are stored as FP16 the windows hold the exact stored pairs
+//    (q[n], q[n+1]) as half2, halving the LDS bytes per update; the
+//    interpolation (1-t) q[n] + t q[n+1] is still evaluated in FP32.
 #include "xct_internal.h"
 
 namespace xct {
@@ -162,8 +169,8 @@ __global__ __launch_bounds__(kBPThreads) void bp_generic_kernel(BPBatch arg)
                 const int n = __float_as_int(par[kk].w) + m;
                 const T *row = q + (int64_t)(k0 + kk) * Nc;
                 const float a0 = row_elem(row, n, Nc);
-                const float a1 = row_elem(row, n + 1, Nc);
-                win[e] = make_float2(a0, a1 - a0);
+                const float d = row_elem(row, n + 1, Nc) - a0;
+                win[e] = make_float2(fmaf(-(float)m, d, a0), d);
             }
             __syncthreads();
             for (int kk = 0; kk < nk; ++kk) {
@@ -176,10 +183,8 @@ __global__ __launch_bounds__(kBPThreads) void bp_generic_kernel(BPBatch arg)
                     float u = ur;
 #pragma unroll
                     for (int aa = 0; aa < 4; ++aa) {
-                        const int n0 = (int)u;
-                        const float tt = __builtin_amdgcn_fractf(u);
-                        const float2 v = w[n0];
-                        acc[bb * 4 + aa] += fmaf(tt, v.y, v.x);
+                        const float2 v = w[(int)u];
+                        acc[bb * 4 + aa] += fmaf(u, v.y, v.x);
                         u += c16;
                     }
                     ur += s16;
@@ -206,25 +211,57 @@ __global__ __launch_bounds__(kBPThreads) void bp_generic_kernel(BPBatch arg)
 
 // ---------------------------------------------------------------- symmetric
 
-// LDS stage: per angle pair kk, params (fbA, fbB, C, S) and window starts
-// (B_A, B_B), then two groups (A, B) of W entries; entry m of a group holds
-// 8 floats: [fwd row k | mirrored row k | fwd row k+H | mirrored row k+H],
-// each an (a, d) pair.
-size_t bp_sym_lds_bytes(int win, int kb)
+// LDS stage of the symmetric kernel: per angle pair kk, the parameters
+// (fbA, fbB, C, S) and window starts (B_A, B_B), then the windows.  Group A is
+// anchored on u(Q, th_k), group B on u(R Q, th_k); each group has four
+// windows: forward row k, mirrored row k, forward row k+H, mirrored row k+H,
+// all indexed by the same local coordinate.
+//  * FP32 rows, structure of arrays, W entries of 16 bytes per array:
+//      [A: row k (a,d) fwd + (a,d) mirrored][A: row k+H][B: row k][B: row k+H]
+//    so the 16-byte reads of a wavefront land on consecutive 16-byte slots
+//    (no bank conflicts while its footprint spans fewer than 16 entries).
+//  * FP16 rows: [A][B], W entries of 16 bytes, each the four windows' exact
+//    stored pairs (q[n], q[n+1]) as half2.
+template <bool HALF>
+constexpr int sym_vec4_per_pair(int W)
 {
-    return ((size_t)kb + ((size_t)kb + 1) / 2) * sizeof(float4) + (size_t)kb * 2 * win * 2 * sizeof(float4);
+    return HALF ? 2 * W : 4 * W;
 }
 
-template <typename T>
+size_t bp_sym_lds_bytes(int win, int kb, bool half)
+{
+    const size_t head = ((size_t)kb + ((size_t)kb + 1) / 2) * sizeof(float4);
+    return head + (size_t)kb * (half ? 2 * win : 4 * win) * sizeof(float4);
+}
+
+__device__ __forceinline__ float lo_half(uint32_t v)
+{
+    return (float)__builtin_bit_cast(f16_t, (uint16_t)(v & 0xffffu));
+}
+
+__device__ __forceinline__ float hi_half(uint32_t v)
+{
+    return (float)__builtin_bit_cast(f16_t, (uint16_t)(v >> 16));
+}
+
+// Raw FP16 bits of the zero-extended row (0 = +0.0 outside the detector).
+__device__ __forceinline__ uint32_t raw_half(const f16_t *row, int n, int nc)
+{
+    return (n >= 0 && n < nc) ? (uint32_t)__builtin_bit_cast(uint16_t, row[n]) : 0u;
+}
+
+template <typename T, int W, bool HALF>
 __global__ __launch_bounds__(kBPThreads) void bp_sym_kernel(BPBatch arg)
 {
+    static_assert(!HALF || sizeof(T) == 2, "FP16 windows need FP16 rows");
     const BPBatch &b = kernarg_batch(arg);
     extern __shared__ float4 lds4[];
     __shared__ int64_t item_slot;
-    const int kb = b.kb, W = b.win;
+    const int kb = b.kb;
     float4 *par = lds4;
     int2 *wstart = reinterpret_cast<int2 *>(lds4 + kb);
-    float4 *win = lds4 + kb + (kb * sizeof(int2) + sizeof(float4) - 1) / sizeof(float4);
+    float4 *win = lds4 + kb + (kb + 1) / 2;
+    constexpr int PER = sym_vec4_per_pair<HALF>(W);
     const int tid = threadIdx.x;
     int px, py;
     thread_lattice(tid, px, py);
@@ -277,19 +314,28 @@ __global__ __launch_bounds__(kBPThreads) void bp_sym_kernel(BPBatch arg)
                 const int rn = M - n;
                 const T *rk = q + (int64_t)(k0 + kk) * Nc;
                 const T *rh = q + (int64_t)(k0 + kk + H) * Nc;
-                const float f0 = row_elem(rk, n, Nc), f1 = row_elem(rk, n + 1, Nc);
-                const float m0 = row_elem(rk, rn, Nc), m1 = row_elem(rk, rn - 1, Nc);
-                const float h0 = row_elem(rh, n, Nc), h1 = row_elem(rh, n + 1, Nc);
-                const float g0 = row_elem(rh, rn, Nc), g1 = row_elem(rh, rn - 1, Nc);
-                win[2 * e] = make_float4(f0, f1 - f0, m0, m1 - m0);
-                win[2 * e + 1] = make_float4(h0, h1 - h0, g0, g1 - g0);
+                float4 *dst = win + kk * PER;
+                if constexpr (HALF) {
+                    const uint32_t f0 = raw_half(rk, n, Nc) | (raw_half(rk, n + 1, Nc) << 16);
+                    const uint32_t m0 = raw_half(rk, rn, Nc) | (raw_half(rk, rn - 1, Nc) << 16);
+                    const uint32_t h0 = raw_half(rh, n, Nc) | (raw_half(rh, n + 1, Nc) << 16);
+                    const uint32_t g0 = raw_half(rh, rn, Nc) | (raw_half(rh, rn - 1, Nc) << 16);
+                    reinterpret_cast<uint4 *>(dst)[g * W + m] = make_uint4(f0, m0, h0, g0);
+                } else {
+                    const float f0 = row_elem(rk, n, Nc), fd = row_elem(rk, n + 1, Nc) - f0;
+                    const float m0 = row_elem(rk, rn, Nc), md = row_elem(rk, rn - 1, Nc) - m0;
+                    const float h0 = row_elem(rh, n, Nc), hd = row_elem(rh, n + 1, Nc) - h0;
+                    const float g0 = row_elem(rh, rn, Nc), gd = row_elem(rh, rn - 1, Nc) - g0;
+                    const float mf = -(float)m;
+                    dst[g * 2 * W + m] = make_float4(fmaf(mf, fd, f0), fd, fmaf(mf, md, m0), md);
+                    dst[g * 2 * W + W + m] = make_float4(fmaf(mf, hd, h0), hd, fmaf(mf, gd, g0), gd);
+                }
             }
             __syncthreads();
             for (int kk = 0; kk < nk; ++kk) {
                 const float4 p = par[kk];
                 const float C = p.z, S = p.w;
-                const float4 *wa = win + (size_t)kk * 4 * W;
-                const float4 *wb = wa + 2 * W;
+                const float4 *wk = win + kk * PER;
                 const float c16 = 16.0f * C, s16 = 16.0f * S;
                 float ua_r = p.x + dxo * C + dyo * S;   // u(Q, th_k) - B_A
                 float ub_r = p.y + dyo * C - dxo * S;   // u(R Q, th_k) - B_B
@@ -299,15 +345,30 @@ __global__ __launch_bounds__(kBPThreads) void bp_sym_kernel(BPBatch arg)
 #pragma unroll
                     for (int aa = 0; aa < 4; ++aa) {
                         const int na = (int)ua, nb = (int)ub;
-                        const float ta = __builtin_amdgcn_fractf(ua);
-                        const float tb = __builtin_amdgcn_fractf(ub);
-                        const float4 a0 = wa[2 * na], a1 = wa[2 * na + 1];
-                        const float4 b0 = wb[2 * nb], b1 = wb[2 * nb + 1];
                         const int pi = bb * 4 + aa;
-                        acc[0][pi] += fmaf(ta, a0.y, a0.x) + fmaf(tb, b1.y, b1.x);  // Q
-                        acc[2][pi] += fmaf(ta, a0.w, a0.z) + fmaf(tb, b1.w, b1.z);  // R^2 Q
-                        acc[3][pi] += fmaf(ta, a1.y, a1.x) + fmaf(tb, b0.w, b0.z);  // R^3 Q
-                        acc[1][pi] += fmaf(ta, a1.w, a1.z) + fmaf(tb, b0.y, b0.x);  // R Q
+                        if constexpr (HALF) {
+                            const uint4 ra = reinterpret_cast<const uint4 *>(wk)[na];
+                            const uint4 rb = reinterpret_cast<const uint4 *>(wk)[W + nb];
+                            const float ta = __builtin_amdgcn_fractf(ua), oa = 1.0f - ta;
+                            const float tb = __builtin_amdgcn_fractf(ub), ob = 1.0f - tb;
+                            // group A: Q, R^2 Q at th_k; R^3 Q, R Q at th_k + pi/2
+                            acc[0][pi] = fmaf(ta, hi_half(ra.x), fmaf(oa, lo_half(ra.x), acc[0][pi]));
+                            acc[2][pi] = fmaf(ta, hi_half(ra.y), fmaf(oa, lo_half(ra.y), acc[2][pi]));
+                            acc[3][pi] = fmaf(ta, hi_half(ra.z), fmaf(oa, lo_half(ra.z), acc[3][pi]));
+                            acc[1][pi] = fmaf(ta, hi_half(ra.w), fmaf(oa, lo_half(ra.w), acc[1][pi]));
+                            // group B: R Q, R^3 Q at th_k; Q, R^2 Q at th_k + pi/2
+                            acc[1][pi] = fmaf(tb, hi_half(rb.x), fmaf(ob, lo_half(rb.x), acc[1][pi]));
+                            acc[3][pi] = fmaf(tb, hi_half(rb.y), fmaf(ob, lo_half(rb.y), acc[3][pi]));
+                            acc[0][pi] = fmaf(tb, hi_half(rb.z), fmaf(ob, lo_half(rb.z), acc[0][pi]));
+                            acc[2][pi] = fmaf(tb, hi_half(rb.w), fmaf(ob, lo_half(rb.w), acc[2][pi]));
+                        } else {
+                            const float4 a0 = wk[na], a1 = wk[W + na];
+                            const float4 b0 = wk[2 * W + nb], b1 = wk[3 * W + nb];
+                            acc[0][pi] += fmaf(ua, a0.y, a0.x) + fmaf(ub, b1.y, b1.x);  // Q
+                            acc[2][pi] += fmaf(ua, a0.w, a0.z) + fmaf(ub, b1.w, b1.z);  // R^2 Q
+                            acc[3][pi] += fmaf(ua, a1.y, a1.x) + fmaf(ub, b0.w, b0.z);  // R^3 Q
+                            acc[1][pi] += fmaf(ua, a1.w, a1.z) + fmaf(ub, b0.y, b0.x);  // R Q
+                        }
                         ua += c16;
                         ub -= s16;
                     }
@@ -353,58 +414,59 @@ static hipError_t prepare(K kernel, size_t lds)
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <typename T>
-static hipError_t launch_generic_t(const BPBatch &b, int grid, size_t lds, hipStream_t s)
+template <typename K>
+static hipError_t launch(K kernel, const BPBatch &b, int grid, size_t lds, hipStream_t s)
 {
-    hipError_t e = prepare(bp_generic_kernel<T>, lds);
+    hipError_t e = prepare(kernel, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(bp_generic_kernel<T>, dim3(grid), dim3(kBPThreads), lds, s, b);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBPThreads), lds, s, b);
     return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t launch_sym_t(const BPBatch &b, int grid, size_t lds, hipStream_t s)
+template <typename K>
+static int occupancy(K kernel, size_t lds)
 {
-    hipError_t e = prepare(bp_sym_kernel<T>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(bp_sym_kernel<T>, dim3(grid), dim3(kBPThreads), lds, s, b);
-    return hipGetLastError();
+    int n = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, kBPThreads, lds);
+    (void)hipGetLastError();
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+int bp_sym_window(int need) { return need <= 96 ? 96 : (need <= 192 ? 192 : 0); }
+
+// The kernel instantiation for (symmetric?, filtered dtype, window) and an
+// action on it: launch, or occupancy query.
+template <typename F>
+static auto with_kernel(bool sym, int dtype, int win, F &&f)
+{
+    if (!sym) {
+        if (dtype == XCT_F32) return f(bp_generic_kernel<float>);
+        if (dtype == XCT_F16) return f(bp_generic_kernel<f16_t>);
+        return f(bp_generic_kernel<bf16_t>);
+    }
+    if (win == 96) {
+        if (dtype == XCT_F32) return f(bp_sym_kernel<float, 96, false>);
+        if (dtype == XCT_F16) return f(bp_sym_kernel<f16_t, 96, true>);
+        return f(bp_sym_kernel<bf16_t, 96, false>);
+    }
+    if (dtype == XCT_F32) return f(bp_sym_kernel<float, 192, false>);
+    if (dtype == XCT_F16) return f(bp_sym_kernel<f16_t, 192, true>);
+    return f(bp_sym_kernel<bf16_t, 192, false>);
 }
 
 hipError_t launch_bp_generic(const BPBatch &b, int dtype, int grid, size_t lds, hipStream_t s)
 {
-    if (dtype == XCT_F32) return launch_generic_t<float>(b, grid, lds, s);
-    if (dtype == XCT_F16) return launch_generic_t<f16_t>(b, grid, lds, s);
-    return launch_generic_t<bf16_t>(b, grid, lds, s);
+    return with_kernel(false, dtype, b.win, [&](auto k) { return launch(k, b, grid, lds, s); });
 }
 
 hipError_t launch_bp_sym(const BPBatch &b, int dtype, int grid, size_t lds, hipStream_t s)
 {
-    if (dtype == XCT_F32) return launch_sym_t<float>(b, grid, lds, s);
-    if (dtype == XCT_F16) return launch_sym_t<f16_t>(b, grid, lds, s);
-    return launch_sym_t<bf16_t>(b, grid, lds, s);
+    return with_kernel(true, dtype, b.win, [&](auto k) { return launch(k, b, grid, lds, s); });
 }
 
-int bp_max_blocks_per_cu(bool sym, int dtype, size_t lds)
+int bp_max_blocks_per_cu(bool sym, int dtype, int win, size_t lds)
 {
-    int n = 0;
-    hipError_t e;
-    if (sym) {
-        if (dtype == XCT_F32)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bp_sym_kernel<float>, kBPThreads, lds);
-        else if (dtype == XCT_F16)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bp_sym_kernel<f16_t>, kBPThreads, lds);
-        else
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bp_sym_kernel<bf16_t>, kBPThreads, lds);
-    } else {
-        if (dtype == XCT_F32)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bp_generic_kernel<float>, kBPThreads, lds);
-        else if (dtype == XCT_F16)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bp_generic_kernel<f16_t>, kBPThreads, lds);
-        else
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bp_generic_kernel<bf16_t>, kBPThreads, lds);
-    }
-    return (e == hipSuccess && n > 0) ? n : 1;
+    return with_kernel(sym, dtype, win, [&](auto k) { return occupancy(k, lds); });
 }
 
 }  // namespace xct

@@ -38,7 +38,7 @@ struct BPBatch {
     int64_t total_items;
     unsigned int *counter;  // persistent work counter, or nullptr (one item per block)
     int32_t n_slabs;
-    int32_t win;            // window entries per angle (per group on the symmetric path)
+    int32_t win;            // window entries per angle and window
     int32_t kb;             // angles (generic) / angle pairs (symmetric) per LDS stage
     int32_t xcd_remap;      // map consecutive items to one XCD (non-persistent launches)
 };
@@ -47,8 +47,9 @@ struct BPBatch {
 hipError_t launch_bp_generic(const BPBatch &b, int dtype, int grid, size_t lds, hipStream_t s);
 hipError_t launch_bp_sym(const BPBatch &b, int dtype, int grid, size_t lds, hipStream_t s);
 size_t bp_generic_lds_bytes(int win, int kb);
-size_t bp_sym_lds_bytes(int win, int kb);
-int bp_max_blocks_per_cu(bool sym, int dtype, size_t lds);
+size_t bp_sym_lds_bytes(int win, int kb, bool half);
+int bp_sym_window(int need);  // window of the symmetric kernel that covers `need` (0: none)
+int bp_max_blocks_per_cu(bool sym, int dtype, int win, size_t lds);
 
 struct FilterArgs {
     const void *in;    // [rows][Nc]

@@ -126,34 +126,64 @@ def radon_ellipses(ell: np.ndarray, geom: Geometry, device="cpu") -> torch.Tenso
     normal theta, is 2 A B sqrt(a^2 - s^2) / a^2 with
     a^2 = A^2 cos^2(theta - phi) + B^2 sin^2(theta - phi); a shifted centre
     shifts s by x0 cos(theta) + y0 sin(theta).
+
+    Ellipses wider than the detector are evaluated on every bin.  The others
+    are evaluated, a group at a time, on the band of bins they can touch and
+    summed in 2^-32 fixed point (int64), so that the result does not depend on
+    the order in which overlapping contributions are added.
     """
     hw = geom.half_width
     npr, nc, pitch, c = geom.n_angles, geom.n_det, geom.det_pitch, float(geom.center)
     th = torch.as_tensor(geom.angles, dtype=F64, device=device)
     ct, st = torch.cos(th), torch.sin(th)
-    out = torch.zeros(npr * nc, dtype=F64, device=device)
-    krow = torch.arange(npr, device=device, dtype=torch.int64)[:, None] * nc
-    for x0, y0, A, B, phi, rho in ell:
-        if rho == 0.0:
-            continue
-        x0, y0, A, B = x0 * hw, y0 * hw, A * hw, B * hw
-        s0 = x0 * ct + y0 * st
-        a2 = (A * torch.cos(th - phi)) ** 2 + (B * torch.sin(th - phi)) ** 2
-        width = int(math.ceil(2.0 * max(A, B) / pitch)) + 3
-        if width >= nc:
-            n = torch.arange(nc, device=device, dtype=torch.int64)[None, :].expand(npr, nc)
-        else:
-            lo = torch.floor(c + (s0 - torch.sqrt(a2)) / pitch).to(torch.int64) - 1
-            n = lo[:, None] + torch.arange(width, device=device, dtype=torch.int64)[None, :]
-        s = (n.to(F64) - c) * pitch - s0[:, None]
-        v = (2.0 * rho * A * B) * torch.sqrt(torch.clamp(a2[:, None] - s * s, min=0.0)) / a2[:, None]
-        inside = (n >= 0) & (n < nc)
-        v = torch.where(inside, v, torch.zeros((), dtype=F64, device=device))
-        idx = krow + torch.clamp(n, 0, nc - 1)
-        # every (angle, bin) appears at most once per ellipse except the
-        # clamped out-of-range entries, which carry exact zeros: deterministic.
-        out.index_add_(0, idx.reshape(-1), v.reshape(-1))
-    return out.view(npr, nc)
+    out = torch.zeros(npr, nc, dtype=F64, device=device)
+    e = np.asarray(ell, dtype=np.float64).reshape(-1, 6)
+    e = e[e[:, RHO] != 0.0]
+    phys = e.copy()
+    phys[:, [X0, Y0, AX, BX]] *= hw
+    widths = np.ceil(2.0 * np.maximum(phys[:, AX], phys[:, BX]) / pitch).astype(np.int64) + 3
+    big = widths >= nc
+
+    def profile(P, n):
+        # P: (G, 6) parameters; n: (G, npr, W) bins -> chord values (G, npr, W)
+        x0, y0, A, B, phi, rho = (P[:, k, None] for k in range(6))       # (G, 1)
+        s0 = x0 * ct[None] + y0 * st[None]                                # (G, npr)
+        a2 = (A * torch.cos(th[None] - phi)) ** 2 + (B * torch.sin(th[None] - phi)) ** 2
+        s = (n.to(F64) - c) * pitch - s0[:, :, None]
+        amp = (2.0 * rho * A * B)[:, :, None]
+        return amp * torch.sqrt(torch.clamp(a2[:, :, None] - s * s, min=0.0)) / a2[:, :, None], s0, a2
+
+    if big.any():
+        nbin = torch.arange(nc, device=device, dtype=torch.int64)[None, None, :].expand(1, npr, nc)
+        for row in phys[big]:
+            v, _, _ = profile(torch.as_tensor(row[None], dtype=F64, device=device), nbin)
+            out += v[0]
+
+    small = phys[~big]
+    if len(small):
+        acc = torch.zeros(npr * nc, dtype=torch.int64, device=device)
+        krow = (torch.arange(npr, device=device, dtype=torch.int64) * nc)[None, :, None]
+        order = np.argsort(widths[~big], kind="stable")
+        small, wsm = small[order], widths[~big][order]
+        i = 0
+        while i < len(small):
+            # group ellipses of similar band width, about 2e7 band samples at a time
+            per = max(1, int(2e7 // (npr * int(wsm[i]))))
+            j = min(len(small), i + per, int(np.searchsorted(wsm, 2 * wsm[i], side="right")))
+            width = int(wsm[j - 1])
+            P = torch.as_tensor(small[i:j], dtype=F64, device=device)
+            x0, y0, A, B, phi = (P[:, k, None] for k in range(5))
+            s0 = x0 * ct[None] + y0 * st[None]
+            a = torch.sqrt((A * torch.cos(th[None] - phi)) ** 2 + (B * torch.sin(th[None] - phi)) ** 2)
+            lo = torch.floor(c + (s0 - a) / pitch).to(torch.int64) - 1        # (G, npr)
+            n = lo[:, :, None] + torch.arange(width, device=device, dtype=torch.int64)
+            v, _, _ = profile(P, n)
+            v = torch.where((n >= 0) & (n < nc), v, torch.zeros((), dtype=F64, device=device))
+            fixed = torch.round(v * 4294967296.0).to(torch.int64)
+            acc.index_add_(0, (krow + torch.clamp(n, 0, nc - 1)).reshape(-1), fixed.reshape(-1))
+            i = j
+        out += acc.view(npr, nc).to(F64) / 4294967296.0
+    return out
 
 
 def rasterize_ellipses(ell: np.ndarray, geom: Geometry, supersample: int = 4,
