@@ -107,10 +107,14 @@ int xct_backproject(const xct_geometry *g, int32_t n_slices, const void *sino, i
                     float *image, float scale, int32_t accumulate, xct_stream stream);
 
 /* Pixel-driven forward projector, the exact transpose of the back-projector:
- *   sino[s][k][n] = (pixel^2 / pitch) sum_{i,j} image[s][i][j] K(u_k(x_j, y_i) - n)
- * FP32 only.  Deterministic (gather form, no atomics). */
+ *   sino[s][k][n] = (accumulate ? sino[s][k][n] : 0)
+ *                   + scale * sum_{i,j} image[s][i][j] K(u_k(x_j, y_i) - n)
+ * The projector P of the least-squares problem uses scale = pixel^2 / pitch
+ * (so that sum_n P x * pitch = sum x * pixel^2); accumulate with a negated
+ * scale forms residuals in one pass.  FP32 only.  Deterministic (gather form,
+ * no atomics). */
 int xct_forward_project(const xct_geometry *g, int32_t n_slices, const float *image,
-                        float *sino, xct_stream stream);
+                        float *sino, float scale, int32_t accumulate, xct_stream stream);
 
 /* One slab of slices sharing a geometry, for xct_fbp_batch. */
 typedef struct {

@@ -48,21 +48,22 @@ def project(x: torch.Tensor, geom, chunk: int = 8) -> torch.Tensor:
 
 def ls_loss_and_grad(x: torch.Tensor, y: torch.Tensor, geom, chunk: int = 4):
     """(||P x - y||^2 as a float64 device scalar, 2 P^T (P x - y) as FP32),
-    computed chunk by chunk of slices.  The gradient is formed as
-    2 s A^T (P x) - 2 s A^T y with two accumulating back-projections, so every
-    arithmetic step runs in the library's kernels."""
+    computed chunk by chunk of slices, holding one chunk's residual at a time.
+    The residual is formed inside the forward projector, which accumulates
+    -P x onto a copy of y (r = y - P x); the loss is an FP64 reduction of r and
+    the gradient one back-projection, -2 P^T r."""
     x = x.contiguous()
     y = y.contiguous()
     S = x.shape[0]
     s = xct.adjoint_scale(geom)
     loss = torch.zeros((), dtype=torch.float64, device=x.device)
     grad = torch.empty_like(x)
-    px = torch.empty((min(chunk, S), geom.n_angles, geom.n_det), dtype=torch.float32, device=x.device)
+    res = torch.empty((min(chunk, S), geom.n_angles, geom.n_det), dtype=torch.float32, device=x.device)
     for s0 in range(0, S, chunk):
         s1 = min(s0 + chunk, S)
-        pc = px[: s1 - s0]
-        xct.xct_forward_project(geom, x[s0:s1], pc)
-        loss += xct.xct_sqdist_f64(pc, y[s0:s1])
-        xct.xct_backproject(geom, pc, grad[s0:s1], 2.0 * s, False)
-        xct.xct_backproject(geom, y[s0:s1], grad[s0:s1], -2.0 * s, True)
+        r = res[: s1 - s0]
+        r.copy_(y[s0:s1])
+        xct.xct_forward_project(geom, x[s0:s1], r, -s, accumulate=True)
+        loss += xct.xct_dot_f64(r, r)
+        xct.xct_backproject(geom, r, grad[s0:s1], -2.0 * s, False)
     return loss, grad

@@ -240,7 +240,7 @@ int device_cus()
 // Window entries per angle for a 64-pixel tile: the detector footprint of the
 // tile spans 63 (|C| + |S|) <= 63 sqrt(2) pixel/pitch bins; 3 more cover the
 // floor, the right tap and the one-bin margin of the anchor.
-int window_entries(double ratio) { return (int)std::ceil(63.0 * std::sqrt(2.0) * ratio + 1e-3) + 3; }
+int window_entries(double ratio) { return (int)std::ceil((kTile - 1) * std::sqrt(2.0) * ratio + 1e-3) + 3; }
 
 bool symmetric_ok(const xct_geometry *g)
 {
@@ -254,6 +254,8 @@ bool symmetric_ok(const xct_geometry *g)
     return true;
 }
 
+int choose_path(const xct_geometry *g) { return symmetric_ok(g) ? kPathSymmetric : kPathGeneric; }
+
 struct BPJob {
     const xct_geometry *g;
     GeoTables t;
@@ -262,31 +264,34 @@ struct BPJob {
     float *image;
     float scale;
     int32_t accumulate;
-    bool sym;
+    int path;
 };
 
-int tiles_of(const BPJob &j, int *tx, int *ty)
+// Tiles per slice as the kernel indexes them (tiles_x, tiles_y) and the work
+// items of the whole slab.
+int64_t plan_tiles(const BPJob &j, int *tx, int *ty)
 {
-    if (j.sym) {
-        const int h = j.g->nx / 2;
-        *tx = *ty = (h + kTile - 1) / kTile;
-    } else {
+    if (j.path == kPathGeneric) {
         *tx = (j.g->nx + kTile - 1) / kTile;
         *ty = (j.g->ny + kTile - 1) / kTile;
+        return (int64_t)*tx * *ty * j.n_slices;
     }
-    return XCT_OK;
+    const int q = (j.g->nx / 2 + kTile - 1) / kTile;  // tiles along a quadrant edge
+    *tx = *ty = q;
+    return (int64_t)q * q * j.n_slices;
 }
 
+// LDS bytes of one angle stage: the symmetric kernel takes 6 angle pairs of
+// 8 FP32 windows of 96 entries (4 workgroups per CU fit in 160 KiB).
 constexpr size_t kGenericStageBytes = 32 * 1024;
-constexpr size_t kSymStageBytes = 37 * 1024;      // 6 angle pairs of FP32 windows
-constexpr size_t kSymHalfStageBytes = 37 * 1024;  // 12 angle pairs of FP16 windows
+constexpr size_t kSymStageBytes = 37 * 1024;
 
-// Launch one back-projection over jobs that all take the same kernel
-// (all symmetric or all generic).  counter != nullptr makes it persistent.
+// Launch one back-projection over jobs that all take the same kernel path.
+// counter != nullptr makes it persistent.
 int launch_bp_jobs(std::vector<BPJob> jobs, int dtype, unsigned int *counter, hipStream_t s)
 {
     if (jobs.empty()) return XCT_OK;
-    const bool sym = jobs[0].sym;
+    const int path = jobs[0].path;
     // largest cost per item first (items of one slab cost the same)
     std::stable_sort(jobs.begin(), jobs.end(),
                      [](const BPJob &a, const BPJob &b) { return a.g->n_angles > b.g->n_angles; });
@@ -298,7 +303,7 @@ int launch_bp_jobs(std::vector<BPJob> jobs, int dtype, unsigned int *counter, hi
         const BPJob &j = jobs[i];
         BPSlab &sl = b.slab[i];
         int tx, ty;
-        tiles_of(j, &tx, &ty);
+        const int64_t n_items = plan_tiles(j, &tx, &ty);
         sl.sino = j.sino;
         sl.image = j.image;
         sl.cs = j.t.cs;
@@ -312,10 +317,10 @@ int launch_bp_jobs(std::vector<BPJob> jobs, int dtype, unsigned int *counter, hi
         sl.n_slices = j.n_slices;
         sl.tiles_x = tx;
         sl.tiles_y = ty;
-        sl.mirror = sym ? (int32_t)std::nearbyint(2.0 * j.g->center) : 0;
+        sl.mirror = path != kPathGeneric ? (int32_t)std::nearbyint(2.0 * j.g->center) : 0;
         sl.scale = j.scale;
         sl.accumulate = j.accumulate;
-        items += (int64_t)tx * ty * j.n_slices;
+        items += n_items;
         W = std::max(W, window_entries(j.g->pixel_size / j.g->det_pitch));
     }
     if (items >= (int64_t)1 << 31) return XCT_ETOOBIG;
@@ -323,12 +328,10 @@ int launch_bp_jobs(std::vector<BPJob> jobs, int dtype, unsigned int *counter, hi
     b.total_items = items;
     b.counter = counter;
     size_t lds;
-    if (sym) {
-        W = bp_sym_window(W);  // the caller only routes windows that fit here
-        const bool half = dtype == XCT_F16;
-        const size_t per_pair = (half ? 2 : 4) * (size_t)W * sizeof(float4) + 24;
-        b.kb = (int)std::max<size_t>(1, (half ? kSymHalfStageBytes : kSymStageBytes) / per_pair);
-        lds = bp_sym_lds_bytes(W, b.kb, half);
+    if (path == kPathSymmetric) {
+        W = bp_sym_window(W);  // choose_path only routes windows that fit here
+        b.kb = (int)std::max<size_t>(1, kSymStageBytes / (4 * (size_t)W * sizeof(float4) + 24));
+        lds = bp_sym_lds_bytes(W, b.kb);
     } else {
         b.kb = (int)std::max<size_t>(1, std::min<size_t>(64, kGenericStageBytes / (8 * (size_t)W + 16)));
         lds = bp_generic_lds_bytes(W, b.kb);
@@ -337,14 +340,14 @@ int launch_bp_jobs(std::vector<BPJob> jobs, int dtype, unsigned int *counter, hi
     if (lds > 160 * 1024) return XCT_ETOOBIG;
     int grid;
     if (counter) {
-        const int per_cu = bp_max_blocks_per_cu(sym, dtype, W, lds);
+        const int per_cu = bp_max_blocks_per_cu(path, dtype, W, lds);
         grid = (int)std::min<int64_t>(items, (int64_t)per_cu * device_cus());
         b.xcd_remap = 0;
     } else {
         grid = (int)items;
         b.xcd_remap = (items % 8 == 0) ? 1 : 0;
     }
-    hipError_t e = sym ? launch_bp_sym(b, dtype, grid, lds, s) : launch_bp_generic(b, dtype, grid, lds, s);
+    hipError_t e = launch_bp(path, b, dtype, grid, lds, s);
     return e == hipSuccess ? XCT_OK : hip_fail(e);
 }
 
@@ -429,17 +432,18 @@ int xct_backproject(const xct_geometry *g, int32_t n_slices, const void *sino, i
     j.image = image;
     j.scale = scale;
     j.accumulate = accumulate ? 1 : 0;
-    j.sym = symmetric_ok(g);
+    j.path = choose_path(g);
     if (int rc = geo_tables(g, &j.t)) return rc;
     return launch_bp_jobs({j}, sino_t, nullptr, (hipStream_t)stream);
 }
 
 int xct_forward_project(const xct_geometry *g, int32_t n_slices, const float *image, float *sino,
-                        xct_stream stream)
+                        float scale, int32_t accumulate, xct_stream stream)
 {
     if (int rc = check_geometry(g, true)) return rc;
     if (int rc = check_slices(g, n_slices)) return rc;
     if (!image || !sino) return XCT_EINVAL;
+    if (!std::isfinite(scale)) return XCT_EINVAL;
     if (n_slices > 65535) return XCT_ETOOBIG;
     GeoTables t;
     if (int rc = geo_tables(g, &t)) return rc;
@@ -448,7 +452,8 @@ int xct_forward_project(const xct_geometry *g, int32_t n_slices, const float *im
     a.sino = sino;
     a.csd = t.csd;
     a.center = g->center;
-    a.scale = (float)(g->pixel_size * g->pixel_size / g->det_pitch);
+    a.scale = scale;
+    a.accumulate = accumulate ? 1 : 0;
     a.n_angles = g->n_angles;
     a.n_det = g->n_det;
     a.nx = g->nx;
@@ -495,7 +500,7 @@ int xct_fbp_batch(const xct_slab *slabs, int32_t n_slabs, int32_t sino_t, int32_
     char *ws = static_cast<char *>(workspace);
     unsigned int *counters = reinterpret_cast<unsigned int *>(ws);
     size_t off = 256;
-    std::vector<BPJob> sym_jobs, gen_jobs;
+    std::vector<BPJob> jobs_by_path[2];
     for (int i = 0; i < n_slabs; ++i) {
         const xct_slab &sl = slabs[i];
         const xct_geometry *g = &sl.geom;
@@ -510,14 +515,15 @@ int xct_fbp_batch(const xct_slab *slabs, int32_t n_slabs, int32_t sino_t, int32_
         j.image = sl.image;
         j.scale = (float)(M_PI / g->n_angles);
         j.accumulate = 0;
-        j.sym = symmetric_ok(g);
+        j.path = choose_path(g);
         if (int rc = geo_tables(g, &j.t)) return rc;
-        (j.sym ? sym_jobs : gen_jobs).push_back(j);
+        jobs_by_path[j.path].push_back(j);
     }
     hipError_t e = launch_fill_u32(counters, 2, 0u, s);
     if (e != hipSuccess) return hip_fail(e);
-    if (int rc = launch_bp_jobs(sym_jobs, filtered_t, counters, s)) return rc;
-    return launch_bp_jobs(gen_jobs, filtered_t, counters + 1, s);
+    for (int p = kPathSymmetric; p >= kPathGeneric; --p)
+        if (int rc = launch_bp_jobs(jobs_by_path[p], filtered_t, counters + p, s)) return rc;
+    return XCT_OK;
 }
 
 size_t xct_reduce_workspace_bytes(int64_t n)

@@ -33,10 +33,7 @@
 //    the detector, the coordinates of R^2 Q at th_k and of R^3 Q and R Q at
 //    th_k + pi/2.  One coordinate and one floor then serve four updates,
 //    read from four windows that share one local coordinate.  The workgroup
-//    owns a tile of the top-left quadrant and its three rotations.  When the
-//    filtered rows are stored as FP16 the windows hold the exact stored pairs
-//    (q[n], q[n+1]) as half2, halving the LDS bytes per update; the
-//    interpolation (1-t) q[n] + t q[n+1] is still evaluated in FP32.
+//    owns a tile of the top-left quadrant and its three rotations.
 #include "xct_internal.h"
 
 namespace xct {
@@ -61,43 +58,72 @@ __device__ __forceinline__ float row_elem(const T *row, int n, int nc)
 }
 
 // The batch descriptor is the kernel's only argument, so it sits at offset 0
-// of the kernarg segment.  Reading it through the segment pointer keeps the
-// dynamically indexed slab table in constant memory (scalar loads) instead of
-// a per-lane private copy.
-__device__ __forceinline__ const BPBatch &kernarg_batch(const BPBatch &)
+// of the kernarg segment.  Reading it through a constant-address-space
+// pointer to that segment keeps the dynamically indexed slab table in scalar
+// loads: every field read from it is wave-uniform (an SGPR), as are the rows
+// and buffer resources derived from it, and nothing is copied to scratch.
+typedef const __attribute__((address_space(4))) BPBatch KBatch;
+
+__device__ __forceinline__ KBatch *kernarg_batch()
 {
-    return *(const BPBatch *)__builtin_amdgcn_kernarg_segment_ptr();
+    return (KBatch *)__builtin_amdgcn_kernarg_segment_ptr();
 }
 
-__device__ __forceinline__ void select_slab(const BPBatch &b, int s, BPSlab &out) { out = b.slab[s]; }
+__device__ __forceinline__ void select_slab(KBatch *b, int s, BPSlab &out)
+{
+    out.sino = b->slab[s].sino;
+    out.image = b->slab[s].image;
+    out.cs = b->slab[s].cs;
+    out.csd = b->slab[s].csd;
+    out.center = b->slab[s].center;
+    out.item_begin = b->slab[s].item_begin;
+    out.n_angles = b->slab[s].n_angles;
+    out.n_det = b->slab[s].n_det;
+    out.nx = b->slab[s].nx;
+    out.ny = b->slab[s].ny;
+    out.n_slices = b->slab[s].n_slices;
+    out.tiles_x = b->slab[s].tiles_x;
+    out.tiles_y = b->slab[s].tiles_y;
+    out.mirror = b->slab[s].mirror;
+    out.scale = b->slab[s].scale;
+    out.accumulate = b->slab[s].accumulate;
+}
 
-__device__ __forceinline__ int find_slab(const BPBatch &b, int64_t item)
+__device__ __forceinline__ int find_slab(KBatch *b, int64_t item)
 {
     int s = 0;
-#pragma unroll
-    for (int i = 1; i < kMaxSlabs; ++i)
-        if (i < b.n_slabs && item >= b.slab[i].item_begin) s = i;
+    const int n = b->n_slabs;
+    for (int i = 1; i < n; ++i)
+        if (item >= b->slab[i].item_begin) s = i;
     return s;
+}
+
+// The same value in every lane, as a scalar: everything derived from it
+// (slab, rows, buffer resources) then stays wave-uniform.
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    return (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v) |
+           ((int64_t)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32);
 }
 
 // Next work item of this workgroup: the block index (optionally remapped so
 // that consecutive items share one XCD's L2), or a grab from the persistent
 // counter.  Returns a value >= total when the workgroup is done.
-__device__ __forceinline__ int64_t next_item(const BPBatch &b, int64_t *slot, int iter)
+__device__ __forceinline__ int64_t next_item(KBatch *b, int64_t *slot, int iter)
 {
-    if (b.counter) {
-        if (threadIdx.x == 0) *slot = (int64_t)atomicAdd(b.counter, 1u);
+    if (b->counter) {
+        if (threadIdx.x == 0) *slot = (int64_t)atomicAdd(b->counter, 1u);
         __syncthreads();
-        int64_t it = *slot;
+        const int64_t it = *slot;
         __syncthreads();
         return it;
     }
-    if (iter > 0) return b.total_items;
+    if (iter > 0) return b->total_items;
     int64_t bid = blockIdx.x;
-    if (b.xcd_remap) {
+    if (b->xcd_remap) {
         // blocks are dispatched round-robin over the 8 XCDs; give XCD x the
         // contiguous item range [x*n/8, (x+1)*n/8)
-        int64_t per = b.total_items >> 3;
+        const int64_t per = b->total_items >> 3;
         bid = (bid & 7) * per + (bid >> 3);
     }
     return bid;
@@ -121,10 +147,10 @@ size_t bp_generic_lds_bytes(int win, int kb)
 template <typename T>
 __global__ __launch_bounds__(kBPThreads) void bp_generic_kernel(BPBatch arg)
 {
-    const BPBatch &b = kernarg_batch(arg);
+    KBatch *b = kernarg_batch();
     extern __shared__ float4 lds4[];
     __shared__ int64_t item_slot;
-    const int kb = b.kb, W = b.win;
+    const int kb = b->kb, W = b->win;
     float4 *par = lds4;                          // (frac anchor, C, S, window start)
     float2 *win = reinterpret_cast<float2 *>(lds4 + kb);
     const int tid = threadIdx.x;
@@ -133,8 +159,8 @@ __global__ __launch_bounds__(kBPThreads) void bp_generic_kernel(BPBatch arg)
     const float dxo = px - 31.5f, dyo = py - 31.5f;
 
     for (int iter = 0;; ++iter) {
-        const int64_t item = next_item(b, &item_slot, iter);
-        if (item >= b.total_items) break;
+        const int64_t item = uniform64(next_item(b, &item_slot, iter));
+        if (item >= b->total_items) break;
         BPSlab sl;
         select_slab(b, find_slab(b, item), sl);
         const int64_t local = item - sl.item_begin;
@@ -215,61 +241,74 @@ __global__ __launch_bounds__(kBPThreads) void bp_generic_kernel(BPBatch arg)
 // (fbA, fbB, C, S) and window starts (B_A, B_B), then the windows.  Group A is
 // anchored on u(Q, th_k), group B on u(R Q, th_k); each group has four
 // windows: forward row k, mirrored row k, forward row k+H, mirrored row k+H,
-// all indexed by the same local coordinate.
-//  * FP32 rows, structure of arrays, W entries of 16 bytes per array:
-//      [A: row k (a,d) fwd + (a,d) mirrored][A: row k+H][B: row k][B: row k+H]
-//    so the 16-byte reads of a wavefront land on consecutive 16-byte slots
-//    (no bank conflicts while its footprint spans fewer than 16 entries).
-//  * FP16 rows: [A][B], W entries of 16 bytes, each the four windows' exact
-//    stored pairs (q[n], q[n+1]) as half2.
-template <bool HALF>
-constexpr int sym_vec4_per_pair(int W)
-{
-    return HALF ? 2 * W : 4 * W;
-}
-
-size_t bp_sym_lds_bytes(int win, int kb, bool half)
+// all indexed by the same local coordinate.  Structure of arrays, W entries
+// of 16 bytes per array:
+//   [A: row k (a,d) fwd + (a,d) mirrored][A: row k+H][B: row k][B: row k+H]
+// so the 16-byte reads of a wavefront land on consecutive 16-byte slots (no
+// bank conflicts while its footprint spans fewer than 16 entries).
+size_t bp_sym_lds_bytes(int win, int kb)
 {
     const size_t head = ((size_t)kb + ((size_t)kb + 1) / 2) * sizeof(float4);
-    return head + (size_t)kb * (half ? 2 * win : 4 * win) * sizeof(float4);
+    return head + (size_t)kb * 4 * win * sizeof(float4);
 }
 
-__device__ __forceinline__ float lo_half(uint32_t v)
+// Buffer resource over one sinogram row: the buffer unit's range check
+// returns 0 for byte offsets at or past the row's end, which gives the zero
+// extension on the far side of the detector without a compare.  Offsets
+// below the row start are redirected (kBeyond) to the same range check.
+constexpr uint32_t kBeyond = 0x40000000u;
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const T *row, int nc)
 {
-    return (float)__builtin_bit_cast(f16_t, (uint16_t)(v & 0xffffu));
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(row), (short)0, nc * (int)sizeof(T),
+                                             0x00020000);
 }
 
-__device__ __forceinline__ float hi_half(uint32_t v)
+// Byte offset of element n of a row (kBeyond for n < 0).
+template <typename T>
+__device__ __forceinline__ uint32_t elem_offset(int n)
 {
-    return (float)__builtin_bit_cast(f16_t, (uint16_t)(v >> 16));
+    return n >= 0 ? (uint32_t)n * (uint32_t)sizeof(T) : kBeyond;
 }
 
-// Raw FP16 bits of the zero-extended row (0 = +0.0 outside the detector).
-__device__ __forceinline__ uint32_t raw_half(const f16_t *row, int n, int nc)
+template <typename T>
+__device__ __forceinline__ float buf_elem(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ float buf_elem<float>(__amdgpu_buffer_rsrc_t r, uint32_t off)
 {
-    return (n >= 0 && n < nc) ? (uint32_t)__builtin_bit_cast(uint16_t, row[n]) : 0u;
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float buf_elem<f16_t>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return (float)__builtin_bit_cast(f16_t, (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float buf_elem<bf16_t>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0) << 16);
 }
 
-template <typename T, int W, bool HALF>
+template <typename T, int W>
 __global__ __launch_bounds__(kBPThreads) void bp_sym_kernel(BPBatch arg)
 {
-    static_assert(!HALF || sizeof(T) == 2, "FP16 windows need FP16 rows");
-    const BPBatch &b = kernarg_batch(arg);
+    KBatch *b = kernarg_batch();
     extern __shared__ float4 lds4[];
     __shared__ int64_t item_slot;
-    const int kb = b.kb;
+    const int kb = b->kb;
     float4 *par = lds4;
     int2 *wstart = reinterpret_cast<int2 *>(lds4 + kb);
     float4 *win = lds4 + kb + (kb + 1) / 2;
-    constexpr int PER = sym_vec4_per_pair<HALF>(W);
+    constexpr int PER = 4 * W;
     const int tid = threadIdx.x;
     int px, py;
     thread_lattice(tid, px, py);
     const float dxo = px - 31.5f, dyo = py - 31.5f;
 
     for (int iter = 0;; ++iter) {
-        const int64_t item = next_item(b, &item_slot, iter);
-        if (item >= b.total_items) break;
+        const int64_t item = uniform64(next_item(b, &item_slot, iter));
+        if (item >= b->total_items) break;
         BPSlab sl;
         select_slab(b, find_slab(b, item), sl);
         const int64_t local = item - sl.item_begin;
@@ -282,7 +321,10 @@ __global__ __launch_bounds__(kBPThreads) void bp_sym_kernel(BPBatch arg)
         const double xc = j0 + 31.5 - 0.5 * (N - 1);
         const double yc = i0 + 31.5 - 0.5 * (N - 1);
         const int Np = sl.n_angles, Nc = sl.n_det, H = Np >> 1, M = sl.mirror;
-        const T *q = static_cast<const T *>(sl.sino) + (int64_t)z * Np * Nc;
+        // slice base, pinned to a scalar so the row buffer resources built from
+        // it are wave-uniform (no waterfall loops around the staging loads)
+        const T *q = reinterpret_cast<const T *>(
+            uniform64(reinterpret_cast<int64_t>(static_cast<const T *>(sl.sino) + (int64_t)z * Np * Nc)));
 
         float acc[4][16];
 #pragma unroll
@@ -304,28 +346,28 @@ __global__ __launch_bounds__(kBPThreads) void bp_sym_kernel(BPBatch arg)
                 wstart[tid] = make_int2((int)BA, (int)BB);
             }
             __syncthreads();
-            for (int e = tid; e < nk * 2 * W; e += kBPThreads) {
-                const int kk = e / (2 * W);
-                const int rem = e - kk * 2 * W;
-                const int g = rem >= W;
-                const int m = rem - g * W;
+            // Each wavefront stages whole angle pairs, 64 entries at a time, so
+            // the two rows of a pair are wave-uniform buffer resources.
+            constexpr int kParts = 2 * W / 64;
+            const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+            for (int unit = wave; unit < nk * kParts; unit += kBPThreads / 64) {
+                const int kk = unit / kParts;
+                const int e = (unit - kk * kParts) * 64 + lane;  // entry of the pair, [0, 2W)
+                const int g = e >= W;
+                const int m = e - g * W;
                 const int2 ws = wstart[kk];
                 const int n = (g ? ws.y : ws.x) + m;
                 const int rn = M - n;
-                const T *rk = q + (int64_t)(k0 + kk) * Nc;
-                const T *rh = q + (int64_t)(k0 + kk + H) * Nc;
+                const auto rk = row_rsrc(q + (int64_t)(k0 + kk) * Nc, Nc);
+                const auto rh = row_rsrc(q + (int64_t)(k0 + kk + H) * Nc, Nc);
+                const uint32_t o0 = elem_offset<T>(n), o1 = elem_offset<T>(n + 1);
+                const uint32_t r0 = elem_offset<T>(rn), r1 = elem_offset<T>(rn - 1);
                 float4 *dst = win + kk * PER;
-                if constexpr (HALF) {
-                    const uint32_t f0 = raw_half(rk, n, Nc) | (raw_half(rk, n + 1, Nc) << 16);
-                    const uint32_t m0 = raw_half(rk, rn, Nc) | (raw_half(rk, rn - 1, Nc) << 16);
-                    const uint32_t h0 = raw_half(rh, n, Nc) | (raw_half(rh, n + 1, Nc) << 16);
-                    const uint32_t g0 = raw_half(rh, rn, Nc) | (raw_half(rh, rn - 1, Nc) << 16);
-                    reinterpret_cast<uint4 *>(dst)[g * W + m] = make_uint4(f0, m0, h0, g0);
-                } else {
-                    const float f0 = row_elem(rk, n, Nc), fd = row_elem(rk, n + 1, Nc) - f0;
-                    const float m0 = row_elem(rk, rn, Nc), md = row_elem(rk, rn - 1, Nc) - m0;
-                    const float h0 = row_elem(rh, n, Nc), hd = row_elem(rh, n + 1, Nc) - h0;
-                    const float g0 = row_elem(rh, rn, Nc), gd = row_elem(rh, rn - 1, Nc) - g0;
+                {
+                    const float f0 = buf_elem<T>(rk, o0), fd = buf_elem<T>(rk, o1) - f0;
+                    const float m0 = buf_elem<T>(rk, r0), md = buf_elem<T>(rk, r1) - m0;
+                    const float h0 = buf_elem<T>(rh, o0), hd = buf_elem<T>(rh, o1) - h0;
+                    const float g0 = buf_elem<T>(rh, r0), gd = buf_elem<T>(rh, r1) - g0;
                     const float mf = -(float)m;
                     dst[g * 2 * W + m] = make_float4(fmaf(mf, fd, f0), fd, fmaf(mf, md, m0), md);
                     dst[g * 2 * W + W + m] = make_float4(fmaf(mf, hd, h0), hd, fmaf(mf, gd, g0), gd);
@@ -346,22 +388,7 @@ __global__ __launch_bounds__(kBPThreads) void bp_sym_kernel(BPBatch arg)
                     for (int aa = 0; aa < 4; ++aa) {
                         const int na = (int)ua, nb = (int)ub;
                         const int pi = bb * 4 + aa;
-                        if constexpr (HALF) {
-                            const uint4 ra = reinterpret_cast<const uint4 *>(wk)[na];
-                            const uint4 rb = reinterpret_cast<const uint4 *>(wk)[W + nb];
-                            const float ta = __builtin_amdgcn_fractf(ua), oa = 1.0f - ta;
-                            const float tb = __builtin_amdgcn_fractf(ub), ob = 1.0f - tb;
-                            // group A: Q, R^2 Q at th_k; R^3 Q, R Q at th_k + pi/2
-                            acc[0][pi] = fmaf(ta, hi_half(ra.x), fmaf(oa, lo_half(ra.x), acc[0][pi]));
-                            acc[2][pi] = fmaf(ta, hi_half(ra.y), fmaf(oa, lo_half(ra.y), acc[2][pi]));
-                            acc[3][pi] = fmaf(ta, hi_half(ra.z), fmaf(oa, lo_half(ra.z), acc[3][pi]));
-                            acc[1][pi] = fmaf(ta, hi_half(ra.w), fmaf(oa, lo_half(ra.w), acc[1][pi]));
-                            // group B: R Q, R^3 Q at th_k; Q, R^2 Q at th_k + pi/2
-                            acc[1][pi] = fmaf(tb, hi_half(rb.x), fmaf(ob, lo_half(rb.x), acc[1][pi]));
-                            acc[3][pi] = fmaf(tb, hi_half(rb.y), fmaf(ob, lo_half(rb.y), acc[3][pi]));
-                            acc[0][pi] = fmaf(tb, hi_half(rb.z), fmaf(ob, lo_half(rb.z), acc[0][pi]));
-                            acc[2][pi] = fmaf(tb, hi_half(rb.w), fmaf(ob, lo_half(rb.w), acc[2][pi]));
-                        } else {
+                        {
                             const float4 a0 = wk[na], a1 = wk[W + na];
                             const float4 b0 = wk[2 * W + nb], b1 = wk[3 * W + nb];
                             acc[0][pi] += fmaf(ua, a0.y, a0.x) + fmaf(ub, b1.y, b1.x);  // Q
@@ -415,58 +442,54 @@ static hipError_t prepare(K kernel, size_t lds)
 }
 
 template <typename K>
-static hipError_t launch(K kernel, const BPBatch &b, int grid, size_t lds, hipStream_t s)
+static hipError_t launch(K kernel, int threads, const BPBatch &b, int grid, size_t lds, hipStream_t s)
 {
     hipError_t e = prepare(kernel, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBPThreads), lds, s, b);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), lds, s, b);
     return hipGetLastError();
 }
 
 template <typename K>
-static int occupancy(K kernel, size_t lds)
+static int occupancy(K kernel, int threads, size_t lds)
 {
     int n = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, kBPThreads, lds);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, lds);
     (void)hipGetLastError();
     return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 int bp_sym_window(int need) { return need <= 96 ? 96 : (need <= 192 ? 192 : 0); }
 
-// The kernel instantiation for (symmetric?, filtered dtype, window) and an
-// action on it: launch, or occupancy query.
+// The kernel instantiation for (path, filtered dtype, window) and an action
+// on it (launch or occupancy query), given the kernel and its block size.
 template <typename F>
-static auto with_kernel(bool sym, int dtype, int win, F &&f)
+static auto with_kernel(int path, int dtype, int win, F &&f)
 {
-    if (!sym) {
-        if (dtype == XCT_F32) return f(bp_generic_kernel<float>);
-        if (dtype == XCT_F16) return f(bp_generic_kernel<f16_t>);
-        return f(bp_generic_kernel<bf16_t>);
+    if (path == kPathGeneric) {
+        if (dtype == XCT_F32) return f(bp_generic_kernel<float>, kBPThreads);
+        if (dtype == XCT_F16) return f(bp_generic_kernel<f16_t>, kBPThreads);
+        return f(bp_generic_kernel<bf16_t>, kBPThreads);
     }
     if (win == 96) {
-        if (dtype == XCT_F32) return f(bp_sym_kernel<float, 96, false>);
-        if (dtype == XCT_F16) return f(bp_sym_kernel<f16_t, 96, true>);
-        return f(bp_sym_kernel<bf16_t, 96, false>);
+        if (dtype == XCT_F32) return f(bp_sym_kernel<float, 96>, kBPThreads);
+        if (dtype == XCT_F16) return f(bp_sym_kernel<f16_t, 96>, kBPThreads);
+        return f(bp_sym_kernel<bf16_t, 96>, kBPThreads);
     }
-    if (dtype == XCT_F32) return f(bp_sym_kernel<float, 192, false>);
-    if (dtype == XCT_F16) return f(bp_sym_kernel<f16_t, 192, true>);
-    return f(bp_sym_kernel<bf16_t, 192, false>);
+    if (dtype == XCT_F32) return f(bp_sym_kernel<float, 192>, kBPThreads);
+    if (dtype == XCT_F16) return f(bp_sym_kernel<f16_t, 192>, kBPThreads);
+    return f(bp_sym_kernel<bf16_t, 192>, kBPThreads);
 }
 
-hipError_t launch_bp_generic(const BPBatch &b, int dtype, int grid, size_t lds, hipStream_t s)
+hipError_t launch_bp(int path, const BPBatch &b, int dtype, int grid, size_t lds, hipStream_t s)
 {
-    return with_kernel(false, dtype, b.win, [&](auto k) { return launch(k, b, grid, lds, s); });
+    return with_kernel(path, dtype, b.win,
+                       [&](auto k, int threads) { return launch(k, threads, b, grid, lds, s); });
 }
 
-hipError_t launch_bp_sym(const BPBatch &b, int dtype, int grid, size_t lds, hipStream_t s)
+int bp_max_blocks_per_cu(int path, int dtype, int win, size_t lds)
 {
-    return with_kernel(true, dtype, b.win, [&](auto k) { return launch(k, b, grid, lds, s); });
-}
-
-int bp_max_blocks_per_cu(bool sym, int dtype, int win, size_t lds)
-{
-    return with_kernel(sym, dtype, win, [&](auto k) { return occupancy(k, lds); });
+    return with_kernel(path, dtype, win, [&](auto k, int threads) { return occupancy(k, threads, lds); });
 }
 
 }  // namespace xct

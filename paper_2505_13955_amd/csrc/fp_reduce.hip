@@ -66,7 +66,8 @@ __global__ __launch_bounds__(256) void fp_gather_kernel(FPArgs a)
             }
         }
     }
-    a.sino[((int64_t)z * a.n_angles + k) * a.n_det + n] = a.scale * sum;
+    float *out = a.sino + ((int64_t)z * a.n_angles + k) * a.n_det + n;
+    *out = a.accumulate ? fmaf(a.scale, sum, *out) : a.scale * sum;
 }
 
 hipError_t launch_forward(const FPArgs &a, hipStream_t s)

@@ -43,13 +43,15 @@ struct BPBatch {
     int32_t xcd_remap;      // map consecutive items to one XCD (non-persistent launches)
 };
 
-// Launchers (return hipError_t of the launch).
-hipError_t launch_bp_generic(const BPBatch &b, int dtype, int grid, size_t lds, hipStream_t s);
-hipError_t launch_bp_sym(const BPBatch &b, int dtype, int grid, size_t lds, hipStream_t s);
+// Back-projection kernels: any geometry, or quarter-turn + mirror symmetric.
+enum { kPathGeneric = 0, kPathSymmetric = 1 };
+
+// Launch (returns hipError_t of the launch) and sizing helpers.
+hipError_t launch_bp(int path, const BPBatch &b, int dtype, int grid, size_t lds, hipStream_t s);
 size_t bp_generic_lds_bytes(int win, int kb);
-size_t bp_sym_lds_bytes(int win, int kb, bool half);
-int bp_sym_window(int need);  // window of the symmetric kernel that covers `need` (0: none)
-int bp_max_blocks_per_cu(bool sym, int dtype, int win, size_t lds);
+size_t bp_sym_lds_bytes(int win, int kb);
+int bp_sym_window(int need);  // window of the symmetric kernel covering `need` (0: none)
+int bp_max_blocks_per_cu(int path, int dtype, int win, size_t lds);
 
 struct FilterArgs {
     const void *in;    // [rows][Nc]
@@ -68,7 +70,8 @@ struct FPArgs {
     float *sino;         // [S][Np][Nc]
     const double2 *csd;  // [Np] (cos, sin) * pixel / pitch
     double center;
-    float scale;         // pixel^2 / pitch
+    float scale;
+    int32_t accumulate;
     int32_t n_angles, n_det, nx, ny, n_slices;
 };
 hipError_t launch_forward(const FPArgs &a, hipStream_t s);

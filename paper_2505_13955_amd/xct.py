@@ -77,11 +77,12 @@ EXPORTS = (
 _lib = None
 
 
-def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+def load_library(path: str | None = None) -> ctypes.CDLL:
     """Load libxct.so (raises if it has not been built)."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2505_13955_amd.build`")
     lib = ctypes.CDLL(path)
@@ -91,7 +92,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     sig = {
         "xct_filter": ([gp, i32, vp, i32, vp, i32, i32, vp], ctypes.c_int),
         "xct_backproject": ([gp, i32, vp, i32, vp, ctypes.c_float, i32, vp], ctypes.c_int),
-        "xct_forward_project": ([gp, i32, vp, vp, vp], ctypes.c_int),
+        "xct_forward_project": ([gp, i32, vp, vp, ctypes.c_float, i32, vp], ctypes.c_int),
         "xct_fbp_workspace_bytes": ([sp, i32, i32], sz),
         "xct_fbp_batch": ([sp, i32, i32, i32, i32, vp, sz, vp], ctypes.c_int),
         "xct_reduce_workspace_bytes": ([i64], sz),
@@ -179,14 +180,18 @@ def xct_backproject(geom, sino: torch.Tensor, image: torch.Tensor, scale: float,
     _check("xct_backproject", rc)
 
 
-def xct_forward_project(geom, image: torch.Tensor, sino: torch.Tensor) -> None:
-    """sino = (pixel^2/pitch) A image."""
+def xct_forward_project(geom, image: torch.Tensor, sino: torch.Tensor, scale: float | None = None,
+                        accumulate: bool = False) -> None:
+    """sino = (accumulate ? sino : 0) + scale * A image; scale defaults to
+    pixel^2/pitch (the projector P)."""
     lib = load_library()
     S = _slices(image, geom, True)
     p_in = _dev(image, "image", (torch.float32,))
     p_out = _dev(sino, "sino", (torch.float32,), (S, geom.n_angles, geom.n_det))
     g, ang = make_geometry(geom)
-    rc = lib.xct_forward_project(ctypes.byref(g), S, p_in, p_out, _stream(image))
+    sc = adjoint_scale(geom) if scale is None else float(scale)
+    rc = lib.xct_forward_project(ctypes.byref(g), S, p_in, p_out, sc, 1 if accumulate else 0,
+                                 _stream(image))
     _check("xct_forward_project", rc)
 
 

@@ -66,7 +66,7 @@ def _geom(**kw):
 def test_geometry_validation(lib, kw, code):
     g, ang = _geom(**kw)
     assert lib.xct_backproject(ctypes.byref(g), 1, FAKE, 0, FAKE, 1.0, 0, None) == code
-    assert lib.xct_forward_project(ctypes.byref(g), 1, FAKE, FAKE, None) == code
+    assert lib.xct_forward_project(ctypes.byref(g), 1, FAKE, FAKE, 1.0, 0, None) == code
 
 
 def test_angle_validation(lib):
@@ -96,7 +96,8 @@ def test_backproject_validation(lib):
     assert lib.xct_backproject(ctypes.byref(g), 1, FAKE, 0, FAKE, float("nan"), 0, None) == EINVAL
     assert lib.xct_backproject(ctypes.byref(g), 1, FAKE, 7, FAKE, 1.0, 0, None) == EDTYPE
     assert lib.xct_backproject(None, 1, FAKE, 0, FAKE, 1.0, 0, None) == EINVAL
-    assert lib.xct_forward_project(ctypes.byref(g), 70000, FAKE, FAKE, None) == ETOOBIG
+    assert lib.xct_forward_project(ctypes.byref(g), 70000, FAKE, FAKE, 1.0, 0, None) == ETOOBIG
+    assert lib.xct_forward_project(ctypes.byref(g), 1, FAKE, FAKE, float("inf"), 0, None) == EINVAL
 
 
 def test_fbp_batch_validation(lib):

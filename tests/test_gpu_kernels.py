@@ -94,6 +94,10 @@ BP_CASES = [
     dict(nx=2, ny=2, n_angles=4, n_det=3, det_pitch=1.0, pixel_size=1.0, center=1.0, angles="uni"),
     dict(nx=192, ny=192, n_angles=48, n_det=150, det_pitch=1.3, pixel_size=0.9, center=74.5, angles="uni"),
     dict(nx=128, ny=128, n_angles=36, n_det=100, det_pitch=1.0, pixel_size=1.0, center=40.0, angles="uni"),
+    # pixels 1.5 bins wide: the symmetric kernel's 192-entry windows
+    dict(nx=128, ny=128, n_angles=40, n_det=280, det_pitch=1.0, pixel_size=1.5, center=139.5, angles="uni"),
+    # pixels 3 bins wide: generic kernel with wide windows
+    dict(nx=60, ny=44, n_angles=21, n_det=260, det_pitch=0.5, pixel_size=1.5, center=129.5, angles="rand"),
 ]
 
 
@@ -158,6 +162,21 @@ def test_backproject_is_deterministic(xct):
         b = xct.backproject(q, g)
         torch.cuda.synchronize()
         assert torch.equal(a, b)
+
+
+def test_forward_accumulate_and_scale(xct):
+    """sino = sino0 - 0.7 A x in one pass (the residual form)."""
+    rng = np.random.default_rng(14)
+    g = _geom(n_angles=30, n_det=80, nx=50, ny=50, det_pitch=1.2, center=40.3,
+              angles=rng.uniform(0, math.pi, 30))
+    x = rng.standard_normal((2, 50, 50))
+    y0 = rng.standard_normal((2, 30, 80))
+    y = to_dev(y0)
+    xct.xct_forward_project(g, to_dev(x), y, -0.7, accumulate=True)
+    torch.cuda.synchronize()
+    ref = y0.astype(np.float32).astype(np.float64) - 0.7 / oracle.adjoint_scale(g) * oracle.forward(
+        x.astype(np.float32).astype(np.float64), g)
+    assert rel_l2(y.cpu().numpy(), ref) < 2e-5
 
 
 # ---------------------------------------------------------------- forward projector
