@@ -269,7 +269,7 @@ struct BPJob {
 
 // Tiles per slice as the kernel indexes them (tiles_x, tiles_y) and the work
 // items of the whole slab.
-int64_t plan_tiles(const BPJob &j, int *tx, int *ty)
+int64_t plan_tiles(const BPJob &j, int sl, int *tx, int *ty)
 {
     if (j.path == kPathGeneric) {
         *tx = (j.g->nx + kTile - 1) / kTile;
@@ -278,13 +278,21 @@ int64_t plan_tiles(const BPJob &j, int *tx, int *ty)
     }
     const int q = (j.g->nx / 2 + kTile - 1) / kTile;  // tiles along a quadrant edge
     *tx = *ty = q;
-    return (int64_t)q * q * j.n_slices;
+    return (int64_t)q * q * ((j.n_slices + sl - 1) / sl);
 }
 
 // LDS bytes of one angle stage: the symmetric kernel takes 6 angle pairs of
-// 8 FP32 windows of 96 entries (4 workgroups per CU fit in 160 KiB).
+// 8 FP32 windows of 96 entries per slice (four 256-thread or two 512-thread
+// workgroups per CU fit in 160 KiB).
+#ifndef XCT_SYM2_STAGE_KB
+#define XCT_SYM2_STAGE_KB 74
+#endif
+#ifndef XCT_SYM_MAX_SLICES
+#define XCT_SYM_MAX_SLICES 2  // slices per work item of the symmetric kernel (1 or 2)
+#endif
 constexpr size_t kGenericStageBytes = 32 * 1024;
 constexpr size_t kSymStageBytes = 37 * 1024;
+constexpr size_t kSym2StageBytes = XCT_SYM2_STAGE_KB * 1024;
 
 // Launch one back-projection over jobs that all take the same kernel path.
 // counter != nullptr makes it persistent.
@@ -295,6 +303,10 @@ int launch_bp_jobs(std::vector<BPJob> jobs, int dtype, unsigned int *counter, hi
     // largest cost per item first (items of one slab cost the same)
     std::stable_sort(jobs.begin(), jobs.end(),
                      [](const BPJob &a, const BPJob &b) { return a.g->n_angles > b.g->n_angles; });
+    // two slices per work item when every slab has at least two
+    int spi = path == kPathSymmetric ? XCT_SYM_MAX_SLICES : 1;
+    for (const BPJob &j : jobs)
+        if (j.n_slices < 2) spi = 1;
     BPBatch b;
     std::memset(&b, 0, sizeof(b));
     int W = 0;
@@ -303,7 +315,7 @@ int launch_bp_jobs(std::vector<BPJob> jobs, int dtype, unsigned int *counter, hi
         const BPJob &j = jobs[i];
         BPSlab &sl = b.slab[i];
         int tx, ty;
-        const int64_t n_items = plan_tiles(j, &tx, &ty);
+        const int64_t n_items = plan_tiles(j, spi, &tx, &ty);
         sl.sino = j.sino;
         sl.image = j.image;
         sl.cs = j.t.cs;
@@ -330,8 +342,9 @@ int launch_bp_jobs(std::vector<BPJob> jobs, int dtype, unsigned int *counter, hi
     size_t lds;
     if (path == kPathSymmetric) {
         W = bp_sym_window(W);  // choose_path only routes windows that fit here
-        b.kb = (int)std::max<size_t>(1, kSymStageBytes / (4 * (size_t)W * sizeof(float4) + 24));
-        lds = bp_sym_lds_bytes(W, b.kb);
+        const size_t budget = spi == 2 ? kSym2StageBytes : kSymStageBytes;
+        b.kb = (int)std::max<size_t>(1, budget / (4 * (size_t)W * spi * sizeof(float4) + 24));
+        lds = bp_sym_lds_bytes(W, b.kb, spi);
     } else {
         b.kb = (int)std::max<size_t>(1, std::min<size_t>(64, kGenericStageBytes / (8 * (size_t)W + 16)));
         lds = bp_generic_lds_bytes(W, b.kb);
@@ -340,14 +353,14 @@ int launch_bp_jobs(std::vector<BPJob> jobs, int dtype, unsigned int *counter, hi
     if (lds > 160 * 1024) return XCT_ETOOBIG;
     int grid;
     if (counter) {
-        const int per_cu = bp_max_blocks_per_cu(path, dtype, W, lds);
+        const int per_cu = bp_max_blocks_per_cu(path, dtype, W, spi, lds);
         grid = (int)std::min<int64_t>(items, (int64_t)per_cu * device_cus());
         b.xcd_remap = 0;
     } else {
         grid = (int)items;
         b.xcd_remap = (items % 8 == 0) ? 1 : 0;
     }
-    hipError_t e = launch_bp(path, b, dtype, grid, lds, s);
+    hipError_t e = launch_bp(path, b, dtype, spi, grid, lds, s);
     return e == hipSuccess ? XCT_OK : hip_fail(e);
 }
 

@@ -165,8 +165,8 @@ __global__ __launch_bounds__(kBPThreads) void bp_generic_kernel(BPBatch arg)
         select_slab(b, find_slab(b, item), sl);
         const int64_t local = item - sl.item_begin;
         const int tiles = sl.tiles_x * sl.tiles_y;
-        const int z = (int)(local / tiles);
-        const int t = (int)(local - (int64_t)z * tiles);
+        const int z = __builtin_amdgcn_readfirstlane((int)(local / tiles));
+        const int t = __builtin_amdgcn_readfirstlane((int)(local - (int64_t)z * tiles));
         const int ty = t / sl.tiles_x, tx = t - ty * sl.tiles_x;
         const int i0 = ty * kTile, j0 = tx * kTile;
         const double xc = j0 + 31.5 - 0.5 * (sl.nx - 1);
@@ -246,10 +246,10 @@ __global__ __launch_bounds__(kBPThreads) void bp_generic_kernel(BPBatch arg)
 //   [A: row k (a,d) fwd + (a,d) mirrored][A: row k+H][B: row k][B: row k+H]
 // so the 16-byte reads of a wavefront land on consecutive 16-byte slots (no
 // bank conflicts while its footprint spans fewer than 16 entries).
-size_t bp_sym_lds_bytes(int win, int kb)
+size_t bp_sym_lds_bytes(int win, int kb, int sl)
 {
     const size_t head = ((size_t)kb + ((size_t)kb + 1) / 2) * sizeof(float4);
-    return head + (size_t)kb * 4 * win * sizeof(float4);
+    return head + (size_t)kb * 4 * win * sl * sizeof(float4);
 }
 
 // Buffer resource over one sinogram row: the buffer unit's range check
@@ -290,20 +290,32 @@ __device__ __forceinline__ float buf_elem<bf16_t>(__amdgpu_buffer_rsrc_t r, uint
     return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0) << 16);
 }
 
-template <typename T, int W>
-__global__ __launch_bounds__(kBPThreads) void bp_sym_kernel(BPBatch arg)
+// SL slices per work item: every slice of a slab shares the geometry, so the
+// coordinates, floors and LDS addresses of one tile serve all SL slices; only
+// the windows differ.  With SL = 2 the workgroup has 512 threads and each
+// keeps 8 pixels x 4 rotations x 2 slices in registers.
+template <int SL>
+constexpr int sym_threads() { return kBPThreads * SL; }
+
+template <typename T, int W, int SL>
+__global__ __launch_bounds__(kBPThreads * SL, 4) void bp_sym_kernel(BPBatch arg)
 {
     KBatch *b = kernarg_batch();
     extern __shared__ float4 lds4[];
     __shared__ int64_t item_slot;
+    constexpr int kThreads = kBPThreads * SL;
+    constexpr int PX = 16 / SL;          // pixels per thread
+    constexpr int ROWS = 4 / SL;         // lattice rows per thread (stride 16 SL)
+    constexpr int PER = 4 * W * SL;      // float4 per angle pair
     const int kb = b->kb;
     float4 *par = lds4;
     int2 *wstart = reinterpret_cast<int2 *>(lds4 + kb);
     float4 *win = lds4 + kb + (kb + 1) / 2;
-    constexpr int PER = 4 * W;
-    const int tid = threadIdx.x;
-    int px, py;
-    thread_lattice(tid, px, py);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // a wave covers an 8 x 8 block, the waves a 16 x 16 SL block; each thread
+    // has pixels (px + 16 a, py + 16 SL c), a < 4, c < ROWS
+    const int px = (lane & 7) | ((wv & 1) << 3);
+    const int py = (lane >> 3) | ((wv >> 1) << 3);
     const float dxo = px - 31.5f, dyo = py - 31.5f;
 
     for (int iter = 0;; ++iter) {
@@ -313,24 +325,30 @@ __global__ __launch_bounds__(kBPThreads) void bp_sym_kernel(BPBatch arg)
         select_slab(b, find_slab(b, item), sl);
         const int64_t local = item - sl.item_begin;
         const int tiles = sl.tiles_x * sl.tiles_y;
-        const int z = (int)(local / tiles);
-        const int t = (int)(local - (int64_t)z * tiles);
+        // slice group and tile (the 64-bit division runs on the vector unit;
+        // pin the results back to scalars)
+        const int zg = __builtin_amdgcn_readfirstlane((int)(local / tiles));
+        const int t = __builtin_amdgcn_readfirstlane((int)(local - (int64_t)zg * tiles));
         const int ty = t / sl.tiles_x, tx = t - ty * sl.tiles_x;
         const int N = sl.nx, half = N >> 1;
         const int i0 = ty * kTile, j0 = tx * kTile;
         const double xc = j0 + 31.5 - 0.5 * (N - 1);
         const double yc = i0 + 31.5 - 0.5 * (N - 1);
         const int Np = sl.n_angles, Nc = sl.n_det, H = Np >> 1, M = sl.mirror;
-        // slice base, pinned to a scalar so the row buffer resources built from
-        // it are wave-uniform (no waterfall loops around the staging loads)
+        const int z0 = zg * SL;
+        const int nsl = min(SL, sl.n_slices - z0);  // slices present in this group
+        // first slice of the group, pinned to a scalar so the row buffer
+        // resources built from it are wave-uniform
         const T *q = reinterpret_cast<const T *>(
-            uniform64(reinterpret_cast<int64_t>(static_cast<const T *>(sl.sino) + (int64_t)z * Np * Nc)));
+            uniform64(reinterpret_cast<int64_t>(static_cast<const T *>(sl.sino) + (int64_t)z0 * Np * Nc)));
 
-        float acc[4][16];
+        float acc[SL][4][PX];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int s = 0; s < SL; ++s)
 #pragma unroll
-            for (int p = 0; p < 16; ++p) acc[r][p] = 0.0f;
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int p = 0; p < PX; ++p) acc[s][r][p] = 0.0f;
 
         for (int k0 = 0; k0 < H; k0 += kb) {
             const int nk = min(kb, H - k0);
@@ -346,32 +364,35 @@ __global__ __launch_bounds__(kBPThreads) void bp_sym_kernel(BPBatch arg)
                 wstart[tid] = make_int2((int)BA, (int)BB);
             }
             __syncthreads();
-            // Each wavefront stages whole angle pairs, 64 entries at a time, so
-            // the two rows of a pair are wave-uniform buffer resources.
+            // Each wavefront stages 64 entries of one angle pair of one slice
+            // at a time, so the two rows are wave-uniform buffer resources.  A
+            // slice missing from the last group stages zeros (empty resource).
             constexpr int kParts = 2 * W / 64;
-            const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-            for (int unit = wave; unit < nk * kParts; unit += kBPThreads / 64) {
-                const int kk = unit / kParts;
-                const int e = (unit - kk * kParts) * 64 + lane;  // entry of the pair, [0, 2W)
+            const int wave = __builtin_amdgcn_readfirstlane(wv);
+            for (int unit = wave; unit < nk * SL * kParts; unit += kThreads / 64) {
+                const int kk = unit / (SL * kParts);
+                const int rest = unit - kk * (SL * kParts);
+                const int s = rest / kParts;
+                const int e = (rest - s * kParts) * 64 + lane;  // entry of the pair, [0, 2W)
                 const int g = e >= W;
                 const int m = e - g * W;
                 const int2 ws = wstart[kk];
                 const int n = (g ? ws.y : ws.x) + m;
                 const int rn = M - n;
-                const auto rk = row_rsrc(q + (int64_t)(k0 + kk) * Nc, Nc);
-                const auto rh = row_rsrc(q + (int64_t)(k0 + kk + H) * Nc, Nc);
+                const T *qs = q + (int64_t)s * Np * Nc;
+                const int len = s < nsl ? Nc : 0;
+                const auto rk = row_rsrc(qs + (int64_t)(k0 + kk) * Nc, len);
+                const auto rh = row_rsrc(qs + (int64_t)(k0 + kk + H) * Nc, len);
                 const uint32_t o0 = elem_offset<T>(n), o1 = elem_offset<T>(n + 1);
                 const uint32_t r0 = elem_offset<T>(rn), r1 = elem_offset<T>(rn - 1);
-                float4 *dst = win + kk * PER;
-                {
-                    const float f0 = buf_elem<T>(rk, o0), fd = buf_elem<T>(rk, o1) - f0;
-                    const float m0 = buf_elem<T>(rk, r0), md = buf_elem<T>(rk, r1) - m0;
-                    const float h0 = buf_elem<T>(rh, o0), hd = buf_elem<T>(rh, o1) - h0;
-                    const float g0 = buf_elem<T>(rh, r0), gd = buf_elem<T>(rh, r1) - g0;
-                    const float mf = -(float)m;
-                    dst[g * 2 * W + m] = make_float4(fmaf(mf, fd, f0), fd, fmaf(mf, md, m0), md);
-                    dst[g * 2 * W + W + m] = make_float4(fmaf(mf, hd, h0), hd, fmaf(mf, gd, g0), gd);
-                }
+                const float f0 = buf_elem<T>(rk, o0), fd = buf_elem<T>(rk, o1) - f0;
+                const float m0 = buf_elem<T>(rk, r0), md = buf_elem<T>(rk, r1) - m0;
+                const float h0 = buf_elem<T>(rh, o0), hd = buf_elem<T>(rh, o1) - h0;
+                const float g0 = buf_elem<T>(rh, r0), gd = buf_elem<T>(rh, r1) - g0;
+                const float mf = -(float)m;
+                float4 *dst = win + kk * PER + s * 4 * W + g * 2 * W + m;
+                dst[0] = make_float4(fmaf(mf, fd, f0), fd, fmaf(mf, md, m0), md);
+                dst[W] = make_float4(fmaf(mf, hd, h0), hd, fmaf(mf, gd, g0), gd);
             }
             __syncthreads();
             for (int kk = 0; kk < nk; ++kk) {
@@ -379,49 +400,56 @@ __global__ __launch_bounds__(kBPThreads) void bp_sym_kernel(BPBatch arg)
                 const float C = p.z, S = p.w;
                 const float4 *wk = win + kk * PER;
                 const float c16 = 16.0f * C, s16 = 16.0f * S;
+                const float cr = 16.0f * SL * C, sr = 16.0f * SL * S;
                 float ua_r = p.x + dxo * C + dyo * S;   // u(Q, th_k) - B_A
                 float ub_r = p.y + dyo * C - dxo * S;   // u(R Q, th_k) - B_B
 #pragma unroll
-                for (int bb = 0; bb < 4; ++bb) {
+                for (int cc = 0; cc < ROWS; ++cc) {
                     float ua = ua_r, ub = ub_r;
 #pragma unroll
                     for (int aa = 0; aa < 4; ++aa) {
                         const int na = (int)ua, nb = (int)ub;
-                        const int pi = bb * 4 + aa;
-                        {
-                            const float4 a0 = wk[na], a1 = wk[W + na];
-                            const float4 b0 = wk[2 * W + nb], b1 = wk[3 * W + nb];
-                            acc[0][pi] += fmaf(ua, a0.y, a0.x) + fmaf(ub, b1.y, b1.x);  // Q
-                            acc[2][pi] += fmaf(ua, a0.w, a0.z) + fmaf(ub, b1.w, b1.z);  // R^2 Q
-                            acc[3][pi] += fmaf(ua, a1.y, a1.x) + fmaf(ub, b0.w, b0.z);  // R^3 Q
-                            acc[1][pi] += fmaf(ua, a1.w, a1.z) + fmaf(ub, b0.y, b0.x);  // R Q
+                        const int pi = cc * 4 + aa;
+#pragma unroll
+                        for (int s = 0; s < SL; ++s) {
+                            const float4 *ws = wk + s * 4 * W;
+                            const float4 a0 = ws[na], a1 = ws[W + na];
+                            const float4 b0 = ws[2 * W + nb], b1 = ws[3 * W + nb];
+                            acc[s][0][pi] += fmaf(ua, a0.y, a0.x) + fmaf(ub, b1.y, b1.x);  // Q
+                            acc[s][2][pi] += fmaf(ua, a0.w, a0.z) + fmaf(ub, b1.w, b1.z);  // R^2 Q
+                            acc[s][3][pi] += fmaf(ua, a1.y, a1.x) + fmaf(ub, b0.w, b0.z);  // R^3 Q
+                            acc[s][1][pi] += fmaf(ua, a1.w, a1.z) + fmaf(ub, b0.y, b0.x);  // R Q
                         }
                         ua += c16;
                         ub -= s16;
                     }
-                    ua_r += s16;
-                    ub_r += c16;
+                    ua_r += sr;
+                    ub_r += cr;
                 }
             }
         }
 
-        float *img = sl.image + (int64_t)z * N * N;
 #pragma unroll
-        for (int bb = 0; bb < 4; ++bb) {
+        for (int s = 0; s < SL; ++s) {
+            if (s >= nsl) break;
+            float *img = sl.image + (int64_t)(z0 + s) * N * N;
 #pragma unroll
-            for (int aa = 0; aa < 4; ++aa) {
-                const int i = i0 + py + 16 * bb, j = j0 + px + 16 * aa;
-                if (i < half && j < half) {
-                    const int pi = bb * 4 + aa;
-                    // Q = (i, j); R Q = (N-1-j, i); R^2 Q = (N-1-i, N-1-j); R^3 Q = (j, N-1-i)
-                    const int64_t idx[4] = {(int64_t)i * N + j, (int64_t)(N - 1 - j) * N + i,
-                                            (int64_t)(N - 1 - i) * N + (N - 1 - j),
-                                            (int64_t)j * N + (N - 1 - i)};
+            for (int cc = 0; cc < ROWS; ++cc) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        float v = sl.scale * acc[r][pi];
-                        if (sl.accumulate) v += img[idx[r]];
-                        img[idx[r]] = v;
+                for (int aa = 0; aa < 4; ++aa) {
+                    const int i = i0 + py + 16 * SL * cc, j = j0 + px + 16 * aa;
+                    if (i < half && j < half) {
+                        const int pi = cc * 4 + aa;
+                        // Q = (i, j); R Q = (N-1-j, i); R^2 Q = (N-1-i, N-1-j); R^3 Q = (j, N-1-i)
+                        const int64_t idx[4] = {(int64_t)i * N + j, (int64_t)(N - 1 - j) * N + i,
+                                                (int64_t)(N - 1 - i) * N + (N - 1 - j),
+                                                (int64_t)j * N + (N - 1 - i)};
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            float v = sl.scale * acc[s][r][pi];
+                            if (sl.accumulate) v += img[idx[r]];
+                            img[idx[r]] = v;
+                        }
                     }
                 }
             }
@@ -461,35 +489,43 @@ static int occupancy(K kernel, int threads, size_t lds)
 
 int bp_sym_window(int need) { return need <= 96 ? 96 : (need <= 192 ? 192 : 0); }
 
-// The kernel instantiation for (path, filtered dtype, window) and an action
-// on it (launch or occupancy query), given the kernel and its block size.
+// The kernel instantiation for (path, filtered dtype, window, slices per
+// item) and an action on it (launch or occupancy query), given the kernel
+// and its block size.
+template <int SL, typename F>
+static auto with_sym(int dtype, int win, F &&f)
+{
+    constexpr int th = sym_threads<SL>();
+    if (win == 96) {
+        if (dtype == XCT_F32) return f(bp_sym_kernel<float, 96, SL>, th);
+        if (dtype == XCT_F16) return f(bp_sym_kernel<f16_t, 96, SL>, th);
+        return f(bp_sym_kernel<bf16_t, 96, SL>, th);
+    }
+    if (dtype == XCT_F32) return f(bp_sym_kernel<float, 192, SL>, th);
+    if (dtype == XCT_F16) return f(bp_sym_kernel<f16_t, 192, SL>, th);
+    return f(bp_sym_kernel<bf16_t, 192, SL>, th);
+}
+
 template <typename F>
-static auto with_kernel(int path, int dtype, int win, F &&f)
+static auto with_kernel(int path, int dtype, int win, int sl, F &&f)
 {
     if (path == kPathGeneric) {
         if (dtype == XCT_F32) return f(bp_generic_kernel<float>, kBPThreads);
         if (dtype == XCT_F16) return f(bp_generic_kernel<f16_t>, kBPThreads);
         return f(bp_generic_kernel<bf16_t>, kBPThreads);
     }
-    if (win == 96) {
-        if (dtype == XCT_F32) return f(bp_sym_kernel<float, 96>, kBPThreads);
-        if (dtype == XCT_F16) return f(bp_sym_kernel<f16_t, 96>, kBPThreads);
-        return f(bp_sym_kernel<bf16_t, 96>, kBPThreads);
-    }
-    if (dtype == XCT_F32) return f(bp_sym_kernel<float, 192>, kBPThreads);
-    if (dtype == XCT_F16) return f(bp_sym_kernel<f16_t, 192>, kBPThreads);
-    return f(bp_sym_kernel<bf16_t, 192>, kBPThreads);
+    return sl == 2 ? with_sym<2>(dtype, win, f) : with_sym<1>(dtype, win, f);
 }
 
-hipError_t launch_bp(int path, const BPBatch &b, int dtype, int grid, size_t lds, hipStream_t s)
+hipError_t launch_bp(int path, const BPBatch &b, int dtype, int sl, int grid, size_t lds, hipStream_t s)
 {
-    return with_kernel(path, dtype, b.win,
+    return with_kernel(path, dtype, b.win, sl,
                        [&](auto k, int threads) { return launch(k, threads, b, grid, lds, s); });
 }
 
-int bp_max_blocks_per_cu(int path, int dtype, int win, size_t lds)
+int bp_max_blocks_per_cu(int path, int dtype, int win, int sl, size_t lds)
 {
-    return with_kernel(path, dtype, win, [&](auto k, int threads) { return occupancy(k, threads, lds); });
+    return with_kernel(path, dtype, win, sl, [&](auto k, int threads) { return occupancy(k, threads, lds); });
 }
 
 }  // namespace xct

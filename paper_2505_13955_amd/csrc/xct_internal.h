@@ -47,11 +47,12 @@ struct BPBatch {
 enum { kPathGeneric = 0, kPathSymmetric = 1 };
 
 // Launch (returns hipError_t of the launch) and sizing helpers.
-hipError_t launch_bp(int path, const BPBatch &b, int dtype, int grid, size_t lds, hipStream_t s);
+// `sl`: slices per work item of the symmetric kernel (1 or 2).
+hipError_t launch_bp(int path, const BPBatch &b, int dtype, int sl, int grid, size_t lds, hipStream_t s);
 size_t bp_generic_lds_bytes(int win, int kb);
-size_t bp_sym_lds_bytes(int win, int kb);
+size_t bp_sym_lds_bytes(int win, int kb, int sl);
 int bp_sym_window(int need);  // window of the symmetric kernel covering `need` (0: none)
-int bp_max_blocks_per_cu(int path, int dtype, int win, size_t lds);
+int bp_max_blocks_per_cu(int path, int dtype, int win, int sl, size_t lds);
 
 struct FilterArgs {
     const void *in;    // [rows][Nc]
