@@ -32,7 +32,13 @@ if ROOT not in sys.path:
 METRIC = "GUPS (voxel×angle updates/s) for FBP, fp32 vs fp16-storage, at stated L2 error"
 FLOPS_PER_UPDATE = 6  # coordinate FMA (2), fraction (1), interpolation FMA (2), accumulate (1)
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+LDS_BYTES_PER_UPDATE = 8  # one (a, d) FP32 pair per interpolation
 HBM_PEAK_GBPS = 8000.0
+# HBM bytes of one FP32 back-projection launch of the full 16-slice slab:
+# rocprofv3 FETCH_SIZE x 2.0 plus WRITE_SIZE x 1.0 (the factors under which a
+# plain 1 GiB device copy reads and writes 1 GiB), from the counter passes in
+# profiles/bp_sym_kernel_slab16_8192.txt.  Valid for that kernel build only.
+BP_TRAFFIC_BYTES = 114_166_434 * 1024 * 2 + 4_651_233 * 1024
 
 
 def parse():
@@ -48,6 +54,8 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy three times (a known "
                          "traffic reference for hardware byte counters)")
+    ap.add_argument("--main-only", action="store_true",
+                    help="time only the 16 x 8192^2 slab (skip the uneven-batch and adjoint-pair legs)")
     ap.add_argument("--sample-rows", type=int, default=32,
                     help="rows of one slice checked against / timed on the FP64 oracle")
     return ap.parse_args()
@@ -57,11 +65,96 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def _timed(torch, stream, fn, steps, warmup):
+    """Mean milliseconds of fn() over `steps` launches, after `warmup` untimed
+    ones, from HIP events on the stream the launches go to."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _alu_roofline(kernel, updates, ms):
+    achieved = FLOPS_PER_UPDATE * updates / (ms * 1e-3) / 1e12
+    return {"kernel": kernel, "bound": "alu", "achieved": achieved,
+            "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_VECTOR_PEAK_TFLOPS}
+
+
+def measure_uneven_batch(xct, torch, configs, encode_storage, stream, steps, warmup):
+    """Filter + back-projection of the uneven batch (24 x 512^2, 12 x 1024^2,
+    4 x 2048^2, BF16-stored, Ram-Lak) in one persistent launch per kernel,
+    against the same slabs launched one at a time."""
+    specs = configs.c5()
+    slabs = []
+    for spec in specs:
+        g = spec.geom
+        p = torch.stack([spec.sinogram(s, device="cuda") for s in range(spec.n_slices)])
+        sb = encode_storage(p, "bf16").contiguous()
+        slabs.append((g, sb, torch.empty((spec.n_slices, g.ny, g.nx), device="cuda")))
+        del p
+    ws = torch.empty(xct.xct_fbp_workspace_bytes(slabs), dtype=torch.uint8, device="cuda")
+    updates = [spec.n_slices * spec.geom.nx * spec.geom.ny * spec.geom.n_angles for spec in specs]
+    ms = _timed(torch, stream, lambda: xct.xct_fbp_batch(slabs, "ram_lak", workspace=ws),
+                steps, warmup)
+    alone = [_timed(torch, stream, lambda sl=sl: xct.xct_fbp_batch([sl], "ram_lak", workspace=ws),
+                    steps, warmup) for sl in slabs]
+    log(f"uneven batch: {ms:.3f} ms in one launch, {sum(alone):.3f} ms slab by slab")
+    return {
+        "workload": "24 x 512^2 (720 angles), 12 x 1024^2 (1440), 4 x 2048^2 (2048); bf16 storage, "
+                    "Ram-Lak; xct_fbp_batch, one persistent back-projection launch",
+        "ms": ms, "gups": sum(updates) / (ms * 1e-3) / 1e9,
+        "slab_by_slab_ms": alone, "slab_by_slab_gups": sum(updates) / (sum(alone) * 1e-3) / 1e9,
+        "updates": sum(updates),
+    }
+
+
+def measure_adjoint_pair(xct, torch, configs, stream, steps, warmup):
+    """Forward projector P, its transpose, and one streamed least-squares
+    gradient (loss ||P x - y||^2 and 2 P^T (P x - y)) on 32 x 1024^2, 1440
+    angles, 1449 bins."""
+    spec = configs.c4()
+    g = spec.geom
+    S = spec.n_slices
+    y = torch.stack([spec.sinogram(s, device="cuda") for s in range(S)]).to(torch.float32)
+    truth = torch.stack([spec.truth(s, device="cuda", supersample=2) for s in range(S)])
+    gen = torch.Generator(device="cuda").manual_seed(4)
+    x = (truth + 0.05 * torch.randn(truth.shape, generator=gen, device="cuda",
+                                    dtype=torch.float64)).to(torch.float32).contiguous()
+    del truth
+    y = y.contiguous()
+    px = torch.empty_like(y)
+    ptg = torch.empty_like(x)
+    sc = xct.adjoint_scale(g)
+    updates = S * g.nx * g.ny * g.n_angles
+    fp_ms = _timed(torch, stream, lambda: xct.xct_forward_project(g, x, px), steps, warmup)
+    bp_ms = _timed(torch, stream, lambda: xct.xct_backproject(g, y, ptg, sc, False), steps, warmup)
+    gr_ms = _timed(torch, stream, lambda: xct.ls_loss_and_grad(x, y, g), steps, warmup)
+    log(f"adjoint pair: P {fp_ms:.3f} ms, P^T {bp_ms:.3f} ms, gradient {gr_ms:.3f} ms")
+    return {
+        "workload": "32 x 1024^2, 1440 angles, 1449 bins; x = phantom + 0.05 N(0,1), y = noisy "
+                    "analytic sinogram",
+        "forward_ms": fp_ms, "forward_gups": updates / (fp_ms * 1e-3) / 1e9,
+        "transpose_ms": bp_ms, "transpose_gups": updates / (bp_ms * 1e-3) / 1e9,
+        "ls_gradient_ms": gr_ms, "ls_gradient_gups": 2 * updates / (gr_ms * 1e-3) / 1e9,
+        "updates_per_operator": updates,
+        "roofline_forward": _alu_roofline("fp_gather_kernel", updates, fp_ms),
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the slab path shards "
-              "by slices with no exchange, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build measures "
+              "one GPU's share of the slice-sharded path, which needs no exchange between GPUs",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -184,6 +277,16 @@ def main():
         results[st] = r
         del sino
 
+    del p64, filt, image
+    torch.cuda.empty_cache()
+    extra = {}
+    if not args.main_only:
+        extra["uneven_batch"] = measure_uneven_batch(xct, torch, configs, encode_storage, stream,
+                                                     args.steps, args.warmup)
+        torch.cuda.empty_cache()
+        extra["adjoint_pair"] = measure_adjoint_pair(xct, torch, configs, stream, args.steps,
+                                                     args.warmup)
+
     main_st = "f32" if "f32" in results else storages[0]
     m = results[main_st]
     bp_s = m["bp_ms"] * 1e-3
@@ -213,18 +316,25 @@ def main():
         "bp_ms": m["bp_ms"],
         "storage": {k: v for k, v in results.items()},
         "roofline": {
-            "kernel": "bp_sym_kernel<float>",
+            "kernel": "bp_sym_kernel<float, 96, 2>",
             "bound": "alu",
             "achieved": achieved,
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": BP_TRAFFIC_BYTES if (main_st == "f32" and args.filtered == "f32"
+                                            and S == 16) else None,
+            "traffic_unit": "bytes per launch",
+            "algorithmic_bytes": (S * g.n_angles * g.n_det * (4 if args.filtered == "f32" else 2)
+                                  + 4 * S * g.nx * g.ny),
             "flops_per_update": FLOPS_PER_UPDATE,
             "updates_per_launch": updates,
+            "lds_bytes_per_update": LDS_BYTES_PER_UPDATE,
+            "lds_bytes_per_clk_per_cu": LDS_BYTES_PER_UPDATE * updates / bp_s / (256 * 2.4e9),
         },
         "cpu_baseline": cpu,
     }
+    out.update(extra)
     print(json.dumps(out), flush=True)
 
 
