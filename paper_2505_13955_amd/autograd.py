@@ -19,7 +19,7 @@ from . import xct
 
 class XctProject(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, x: torch.Tensor, geom, chunk: int = 8):
+    def forward(ctx, x: torch.Tensor, geom, chunk: int = 16):
         x = x.contiguous()
         ctx.geom = geom
         ctx.chunk = chunk
@@ -41,12 +41,12 @@ class XctProject(torch.autograd.Function):
         return gx, None, None
 
 
-def project(x: torch.Tensor, geom, chunk: int = 8) -> torch.Tensor:
+def project(x: torch.Tensor, geom, chunk: int = 16) -> torch.Tensor:
     """P x for x of shape (S, N_y, N_x), differentiable in x."""
     return XctProject.apply(x, geom, chunk)
 
 
-def ls_loss_and_grad(x: torch.Tensor, y: torch.Tensor, geom, chunk: int = 4):
+def ls_loss_and_grad(x: torch.Tensor, y: torch.Tensor, geom, chunk: int = 16):
     """(||P x - y||^2 as a float64 device scalar, 2 P^T (P x - y) as FP32),
     computed chunk by chunk of slices, holding one chunk's residual at a time.
     The residual is formed inside the forward projector, which accumulates

@@ -70,9 +70,17 @@ struct FilterTables {
     float *H = nullptr;
 };
 
+struct FPTables {
+    FPAngle *ang = nullptr;
+    FPBlock *blocks = nullptr;
+    int n_blocks = 0;
+    int rows[2] = {0, 0}, pitch[2] = {0, 0};  // staging shape for 1 and 4 slices per workgroup
+};
+
 std::mutex g_mu;
 std::unordered_map<std::string, GeoTables> g_geo;
 std::unordered_map<std::string, FilterTables> g_filt;
+std::unordered_map<std::string, FPTables> g_fp;
 
 template <typename T>
 void key_append(std::string &k, const T &v)
@@ -122,6 +130,50 @@ int geo_tables(const xct_geometry *g, GeoTables *out)
         return hip_fail(e);
     }
     g_geo.emplace(key, t);
+    *out = t;
+    return XCT_OK;
+}
+
+// Forward-projector plan of a geometry (angle table, angle blocks, staging
+// shape), built on the host in FP64 and cached on the device.
+int fp_tables(const xct_geometry *g, FPTables *out)
+{
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    std::string key;
+    key_append(key, dev);
+    key_append(key, g->pixel_size / g->det_pitch);
+    key_append(key, g->center);
+    key_append(key, g->nx);
+    key_append(key, g->ny);
+    key_append(key, g->n_det);
+    key.append(reinterpret_cast<const char *>(g->angles), sizeof(double) * g->n_angles);
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_fp.find(key);
+    if (it != g_fp.end()) {
+        *out = it->second;
+        return XCT_OK;
+    }
+    std::vector<FPAngle> ang;
+    std::vector<FPBlock> blocks;
+    FPTables t;
+    if (int rc = fp_plan(g, ang, blocks, 1, &t.rows[0], &t.pitch[0])) return rc;
+    // four slices per workgroup when their staging fits (not for strips many
+    // pixels wide)
+    if (fp_plan(g, ang, blocks, 4, &t.rows[1], &t.pitch[1]) != XCT_OK) t.rows[1] = 0;
+    t.n_blocks = (int)blocks.size();
+    hipError_t e = hipMalloc(&t.ang, sizeof(FPAngle) * ang.size());
+    if (e == hipSuccess) e = hipMalloc(&t.blocks, sizeof(FPBlock) * blocks.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(t.ang, ang.data(), sizeof(FPAngle) * ang.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(t.blocks, blocks.data(), sizeof(FPBlock) * blocks.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (t.ang) (void)hipFree(t.ang);
+        if (t.blocks) (void)hipFree(t.blocks);
+        return hip_fail(e);
+    }
+    g_fp.emplace(key, t);
     *out = t;
     return XCT_OK;
 }
@@ -400,8 +452,13 @@ void xct_cache_clear(void)
         (void)hipFree(kv.second.tw);
         (void)hipFree(kv.second.H);
     }
+    for (auto &kv : g_fp) {
+        (void)hipFree(kv.second.ang);
+        (void)hipFree(kv.second.blocks);
+    }
     g_geo.clear();
     g_filt.clear();
+    g_fp.clear();
 }
 
 int xct_filter(const xct_geometry *g, int32_t n_slices, const void *sino, int32_t sino_t,
@@ -458,13 +515,20 @@ int xct_forward_project(const xct_geometry *g, int32_t n_slices, const float *im
     if (!image || !sino) return XCT_EINVAL;
     if (!std::isfinite(scale)) return XCT_EINVAL;
     if (n_slices > 65535) return XCT_ETOOBIG;
-    GeoTables t;
-    if (int rc = geo_tables(g, &t)) return rc;
+    FPTables t;
+    if (int rc = fp_tables(g, &t)) return rc;
     FPArgs a;
     a.image = image;
     a.sino = sino;
-    a.csd = t.csd;
-    a.center = g->center;
+    a.ang = t.ang;
+    a.blocks = t.blocks;
+    a.n_blocks = t.n_blocks;
+    a.bin_blocks = (g->n_det + kFPBins - 1) / kFPBins;
+    // four slices per workgroup share coordinates and weights; a call with
+    // one or two slices keeps one per workgroup
+    const int sl = (n_slices >= 3 && t.rows[1] > 0) ? 4 : 1;
+    a.rows = t.rows[sl == 4];
+    a.pitch = t.pitch[sl == 4];
     a.scale = scale;
     a.accumulate = accumulate ? 1 : 0;
     a.n_angles = g->n_angles;
@@ -472,7 +536,7 @@ int xct_forward_project(const xct_geometry *g, int32_t n_slices, const float *im
     a.nx = g->nx;
     a.ny = g->ny;
     a.n_slices = n_slices;
-    hipError_t e = launch_forward(a, (hipStream_t)stream);
+    hipError_t e = launch_forward(a, sl, (hipStream_t)stream);
     return e == hipSuccess ? XCT_OK : hip_fail(e);
 }
 

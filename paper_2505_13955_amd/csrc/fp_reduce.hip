@@ -1,81 +1,339 @@
 // Forward projector (transpose of the back-projector) and FP64 reductions.
 //
-// Forward projector, gather form: one thread per (slice, angle, bin) sums the
-// pixels whose hat weight K(u - n) is non-zero for that bin.  For an angle
-// whose ray direction is closer to the y axis (|C| >= |S|) the thread walks the
-// image rows: in row i the bin's centre line crosses x at column
-//   j*(i) = (n - c - y_i S) / C + (N_x - 1)/2,
-// which moves by -S/C per row (tracked in FP64), and only the columns within
-// 1/|C| of j* carry weight 1 - |j - j*| |C|.  Otherwise the roles of rows and
-// columns swap.  No atomics, fixed summation order: the output is
-// deterministic and its weights are exactly the back-projector's hat weights.
+// Forward projector, gather form: bin n of angle k sums the pixels whose hat
+// weight K(u - n) is non-zero,
+//   (P x)[k][n] = scale sum_{v,w} x(v, w) max(0, 1 - |A v + B w + u0 - n|),
+// where w is the image axis the rays are walked along (rows when |cos| >=
+// |sin|, else columns) and v the other, so |A| >= |B| and along each walk step
+// a bin's strip crosses at most floor(2/|A|) + 1 pixels, centred on
+//   v*(n, w) = (n - u0 - B w) / A.
+// A workgroup takes one block of up to 16 consecutive angles that share the
+// walk axis and one block of 256 bins (a thread per bin).  It walks the image
+// a few steps at a time: it stages into LDS, with coalesced reads, the
+// rectangle of pixels those strips can touch (zeros outside the image), then
+// every thread adds its taps for every angle of the block.  Per angle and
+// stage a thread anchors its crossing in FP64 and keeps an integer index plus
+// an FP32 offset below the staged rows' count, so the hat weights carry
+// rounding of the order of 2^-19 pixel.  Fixed summation order: the output is
+// deterministic.
 //
 // Reductions: a fixed grid of workgroups accumulates FP64 partial sums
 // (wavefront shuffles, then LDS), and one workgroup sums the partials in a
 // fixed order, so results are reproducible bit for bit.
+#include <cmath>
+
 #include "xct_internal.h"
 
 namespace xct {
 
-__global__ __launch_bounds__(256) void fp_gather_kernel(FPArgs a)
+// ---------------------------------------------------------------- forward projector
+
+// SL slices per workgroup: the slices of one call share the geometry, so one
+// thread's crossings, tap indices and hat weights serve SL slices; the staged
+// pixels hold SL values (float4 for four slices).
+template <int SL> struct FPVec;
+template <> struct FPVec<1> {
+    typedef float T;
+    static __device__ __forceinline__ T pack(const float *x) { return x[0]; }
+    static __device__ __forceinline__ float get(const T &v, int) { return v; }
+    static __device__ __forceinline__ T zero() { return 0.0f; }
+    static __device__ __forceinline__ T fma(float w, const T &x, const T &s) { return fmaf(w, x, s); }
+};
+template <> struct FPVec<4> {
+    typedef float4 T;
+    static __device__ __forceinline__ T pack(const float *x) { return make_float4(x[0], x[1], x[2], x[3]); }
+    static __device__ __forceinline__ float get(const T &v, int i)
+    {
+        return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+    }
+    static __device__ __forceinline__ T zero() { return make_float4(0.0f, 0.0f, 0.0f, 0.0f); }
+    static __device__ __forceinline__ T fma(float w, const T &x, const T &s)
+    {
+        return make_float4(fmaf(w, x.x, s.x), fmaf(w, x.y, s.y), fmaf(w, x.z, s.z), fmaf(w, x.w, s.w));
+    }
+};
+
+template <int SL>
+__global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
 {
-    const int nblk = (a.n_det + 255) >> 8;
-    const int k = blockIdx.x / nblk;
-    const int n = (blockIdx.x - k * nblk) * 256 + threadIdx.x;
-    const int z = blockIdx.y;
-    if (n >= a.n_det) return;
-    const double2 cd = a.csd[k];
-    const float *img = a.image + (int64_t)z * a.nx * a.ny;
-    const double C = cd.x, S = cd.y;
-    float sum = 0.0f;
-    if (fabs(C) >= fabs(S)) {
-        const double inv = 1.0 / C;
-        const double y0 = -0.5 * (a.ny - 1);
-        double jr = (n - a.center - y0 * S) * inv + 0.5 * (a.nx - 1);
-        const double step = -S * inv;
-        const double hw = fabs(inv);
-        const float cf = (float)fabs(C);
-        const int mmax = (int)floor(2.0 * hw) + 1;
-        for (int i = 0; i < a.ny; ++i, jr += step) {
-            const double lo = ceil(jr - hw);
-            const int jl = (int)lo;
-            const float f = (float)(jr - lo);
-            const float *row = img + (int64_t)i * a.nx;
-            for (int m = 0; m <= mmax; ++m) {
-                const int j = jl + m;
-                const float w = 1.0f - fabsf(((float)m - f) * cf);
-                if (j >= 0 && j < a.nx && w > 0.0f) sum += w * row[j];
+    typedef FPVec<SL> V;
+    typedef typename V::T VT;
+    constexpr int kStageBatch = SL == 1 ? 8 : 4;  // staged pixels in flight per thread
+    constexpr int kUnroll = SL == 1 ? 4 : 2;      // walk steps per unrolled body
+    __shared__ VT tile[kFPLdsFloats / SL];
+    __shared__ int2 range;  // (first staged cross index, staged width)
+    const int tid = threadIdx.x;
+    const int blk = blockIdx.x / a.bin_blocks;
+    const int bb = blockIdx.x - blk * a.bin_blocks;
+    const int z0 = blockIdx.y * SL;
+    const int nsl = min(SL, a.n_slices - z0);  // slices present in this group
+    const FPBlock B = a.blocks[blk];
+    const int walk = B.walk, count = B.count, k0 = B.k0;
+    const int nv = walk ? a.ny : a.nx, nw = walk ? a.nx : a.ny;
+    const int n0 = bb * kFPBins;
+    const int n1 = min(n0 + kFPBins - 1, a.n_det - 1);
+    const int n = min(n0 + tid, a.n_det - 1);  // threads past the last bin shadow it
+    const int64_t plane = (int64_t)a.nx * a.ny;
+    const float *img = a.image + (int64_t)z0 * plane;
+    const int pitch = a.pitch, rows = a.rows;
+    const int lg_rows = __builtin_ctz(rows);
+
+    VT acc[kFPAngles];
+#pragma unroll
+    for (int q = 0; q < kFPAngles; ++q) acc[q] = V::zero();
+
+    for (int w0 = 0; w0 < nw; w0 += rows) {
+        const int rc = min(rows, nw - w0);
+        __syncthreads();  // the previous stage's readers are done with tile and range
+        if (tid < 64) {
+            // cross range of the block's strips over this stage: v* is linear
+            // in (n, w), so its extremes sit at the corners
+            double lo = 1e300, hi = -1e300;
+            if (tid < 4 * count) {
+                const FPAngle p = a.ang[k0 + (tid >> 2)];
+                const double nn = (tid & 1) ? n1 : n0;
+                const double ww = (tid & 2) ? w0 + rc - 1 : w0;
+                const double vs = (nn - p.u0 - p.B * ww) * p.invA;
+                const double h = 1.0 / fabs(p.A);
+                lo = vs - h;
+                hi = vs + h;
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                lo = fmin(lo, __shfl_xor(lo, off, 64));
+                hi = fmax(hi, __shfl_xor(hi, off, 64));
+            }
+            if (tid == 0) {
+                const int vlo = (int)floor(lo) - 1;
+                const int vhi = (int)ceil(hi) + 1;
+                range = make_int2(vlo, min(vhi - vlo + 2, pitch));
             }
         }
-    } else {
-        const double inv = 1.0 / S;
-        const double x0 = -0.5 * (a.nx - 1);
-        double ir = (n - a.center - x0 * C) * inv + 0.5 * (a.ny - 1);
-        const double step = -C * inv;
-        const double hw = fabs(inv);
-        const float sf = (float)fabs(S);
-        const int mmax = (int)floor(2.0 * hw) + 1;
-        for (int j = 0; j < a.nx; ++j, ir += step) {
-            const double lo = ceil(ir - hw);
-            const int il = (int)lo;
-            const float f = (float)(ir - lo);
-            for (int m = 0; m <= mmax; ++m) {
-                const int i = il + m;
-                const float w = 1.0f - fabsf(((float)m - f) * sf);
-                if (i >= 0 && i < a.ny && w > 0.0f) sum += w * img[(int64_t)i * a.nx + j];
+        __syncthreads();
+        const int vlo = range.x, width = range.y;
+        if (vlo + width <= 0 || vlo >= nv) continue;  // strips miss the image here
+
+        // Stage walk steps w0 .. w0+rc-1, cross indices vlo .. vlo+width-1,
+        // as a flat range of pixels, several in flight per thread.  Walking
+        // rows, consecutive pixels run along an image row; walking columns,
+        // `rows` consecutive columns of one image row are read together.
+        // (f + 1/2) / width in FP32 recovers the staged row of pixel f
+        // exactly: the quotient is below 16, its rounding error below 2^-19,
+        // and its distance to an integer at least 1/(2 width) >= 2^-14.
+        {
+            const int total = walk ? width * rows : width * rc;
+            const float invw = 1.0f / (float)width;
+            for (int fb = 0; fb < total; fb += kStageBatch * kFPBins) {
+                VT val[kStageBatch];
+                int dst[kStageBatch];
+#pragma unroll
+                for (int i = 0; i < kStageBatch; ++i) {
+                    const int f = fb + i * kFPBins + tid;
+                    int r, c;
+                    if (walk == 0) {
+                        r = (int)(((float)f + 0.5f) * invw);
+                        c = f - r * width;
+                    } else {
+                        r = f & (rows - 1);
+                        c = f >> lg_rows;
+                    }
+                    const int v = vlo + c;
+                    float x[SL];
+#pragma unroll
+                    for (int sl = 0; sl < SL; ++sl) x[sl] = 0.0f;
+                    if (f < total && r < rc && v >= 0 && v < nv) {
+                        const int64_t off = walk ? (int64_t)v * a.nx + w0 + r : (int64_t)(w0 + r) * a.nx + v;
+#pragma unroll
+                        for (int sl = 0; sl < SL; ++sl)
+                            if (sl < nsl) x[sl] = img[sl * plane + off];
+                    }
+                    val[i] = V::pack(x);
+                    dst[i] = f < total ? r * pitch + c : -1;
+                }
+#pragma unroll
+                for (int i = 0; i < kStageBatch; ++i)
+                    if (dst[i] >= 0) tile[dst[i]] = val[i];
+            }
+        }
+        __syncthreads();
+
+#pragma unroll
+        for (int q = 0; q < kFPAngles; ++q) {
+            if (q < count) {
+                const FPAngle p = a.ang[k0 + q];
+                const double rel = ((double)n - p.u0 - p.B * (double)w0) * p.invA - (double)vlo;
+                // skip the stage for this angle when no bin of the wavefront
+                // has a strip that reaches the image in these walk steps
+                const float r0f = (float)rel, r1f = fmaf((float)(rc - 1), p.dv, r0f);
+                const bool hits = (n0 + tid < a.n_det) && fmaxf(r0f, r1f) + p.hw > (float)(-vlo) - 1.0f &&
+                                  fminf(r0f, r1f) - p.hw < (float)(nv - vlo);
+                if (__builtin_amdgcn_ballot_w64(hits) == 0) continue;
+                const int bi = (int)floor(rel);
+                const float f0 = (float)(rel - (double)bi);
+                const VT *base = tile + bi;
+                VT s = acc[q];
+                int r = 0;
+                if (p.taps <= 3) {
+                    // hat at most three pixels wide (|A| > 2/3): a fixed
+                    // three-tap body, a few walk steps at a time so their LDS
+                    // reads are in flight together.  A tap past the hat gets
+                    // weight 0 and stays inside the staged width.
+                    for (; r + kUnroll <= rc; r += kUnroll) {
+                        float t[kUnroll];
+                        VT x[kUnroll][3];
+#pragma unroll
+                        for (int u = 0; u < kUnroll; ++u) {
+                            const float vloc = fmaf((float)(r + u), p.dv, f0);
+                            const float vl = ceilf(vloc - p.hw);
+                            t[u] = vl - vloc;
+                            const VT *src = base + (r + u) * pitch + (int)vl;
+#pragma unroll
+                            for (int m = 0; m < 3; ++m) x[u][m] = src[m];
+                        }
+#pragma unroll
+                        for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+                            for (int m = 0; m < 3; ++m)
+                                s = V::fma(fmaxf(fmaf(-p.absA, fabsf(t[u] + (float)m), 1.0f), 0.0f),
+                                           x[u][m], s);
+                    }
+                }
+                for (; r < rc; ++r) {
+                    const float vloc = fmaf((float)r, p.dv, f0);
+                    const float vl = ceilf(vloc - p.hw);
+                    const float t = vl - vloc;
+                    const VT *src = base + r * pitch + (int)vl;
+                    for (int m = 0; m < p.taps; ++m) {
+                        const float wgt = fmaxf(fmaf(-p.absA, fabsf(t + (float)m), 1.0f), 0.0f);
+                        s = V::fma(wgt, src[m], s);
+                    }
+                }
+                acc[q] = s;
             }
         }
     }
-    float *out = a.sino + ((int64_t)z * a.n_angles + k) * a.n_det + n;
-    *out = a.accumulate ? fmaf(a.scale, sum, *out) : a.scale * sum;
+
+    if (n0 + tid < a.n_det) {
+#pragma unroll
+        for (int q = 0; q < kFPAngles; ++q) {
+            if (q < count) {
+#pragma unroll
+                for (int sl = 0; sl < SL; ++sl) {
+                    if (sl < nsl) {
+                        float *out = a.sino + ((int64_t)(z0 + sl) * a.n_angles + k0 + q) * a.n_det + n0 + tid;
+                        const float v = V::get(acc[q], sl);
+                        *out = a.accumulate ? fmaf(a.scale, v, *out) : a.scale * v;
+                    }
+                }
+            }
+        }
+    }
 }
 
-hipError_t launch_forward(const FPArgs &a, hipStream_t s)
+hipError_t launch_forward(const FPArgs &a, int sl, hipStream_t s)
 {
-    dim3 grid((unsigned)(((a.n_det + 255) / 256) * a.n_angles), a.n_slices);
+    dim3 grid((unsigned)(a.n_blocks * a.bin_blocks), (unsigned)((a.n_slices + sl - 1) / sl));
     (void)hipGetLastError();
-    hipLaunchKernelGGL(fp_gather_kernel, grid, dim3(256), 0, s, a);
+    if (sl == 4)
+        hipLaunchKernelGGL(fp_tile_kernel<4>, grid, dim3(kFPBins), 0, s, a);
+    else
+        hipLaunchKernelGGL(fp_tile_kernel<1>, grid, dim3(kFPBins), 0, s, a);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- forward projector plan
+
+namespace {
+
+constexpr double kFPSpread = 64.0;  // largest spread of one block's crossings (pixels)
+
+double vstar(const FPAngle &p, double n, double w) { return (n - p.u0 - p.B * w) * p.invA; }
+
+// Staged width (plus slack) of a block over the bins n0.. n0+255 and walk
+// steps w0 .. w0+rows-1, computed as the kernel computes it.
+int stage_width(const std::vector<FPAngle> &ang, const FPBlock &b, int n0, int w0, int rows)
+{
+    double lo = 1e300, hi = -1e300;
+    for (int q = 0; q < b.count; ++q) {
+        const FPAngle &p = ang[b.k0 + q];
+        const double h = 1.0 / std::fabs(p.A);
+        for (int c = 0; c < 4; ++c) {
+            const double vs = vstar(p, (c & 1) ? n0 + kFPBins - 1 : n0, (c & 2) ? w0 + rows - 1 : w0);
+            lo = std::min(lo, vs - h);
+            hi = std::max(hi, vs + h);
+        }
+    }
+    return ((int)std::ceil(hi) + 1) - ((int)std::floor(lo) - 1) + 2 + 2;
+}
+
+}  // namespace
+
+int fp_plan(const xct_geometry *g, std::vector<FPAngle> &ang, std::vector<FPBlock> &blocks, int sl,
+            int *rows_out, int *pitch_out)
+{
+    const double r = g->pixel_size / g->det_pitch;
+    const double cx = 0.5 * (g->nx - 1), cy = 0.5 * (g->ny - 1);
+    const int np = g->n_angles, nc = g->n_det;
+    ang.resize(np);
+    std::vector<int> walk(np);
+    for (int k = 0; k < np; ++k) {
+        const double C = std::cos(g->angles[k]) * r, S = std::sin(g->angles[k]) * r;
+        FPAngle &p = ang[k];
+        walk[k] = std::fabs(C) >= std::fabs(S) ? 0 : 1;
+        p.A = walk[k] ? S : C;
+        p.B = walk[k] ? C : S;
+        p.u0 = g->center - C * cx - S * cy;
+        p.invA = 1.0 / p.A;
+        p.dv = (float)(-p.B / p.A);
+        p.hw = (float)(1.0 / std::fabs(p.A));
+        p.absA = (float)std::fabs(p.A);
+        p.taps = (int)std::floor(2.0 / std::fabs(p.A)) + 1;
+    }
+    // greedy runs of angles: same walk axis, crossings within kFPSpread pixels
+    // of each other everywhere (the spread is linear in (n, w): check corners)
+    blocks.clear();
+    for (int k = 0; k < np;) {
+        const int nw = walk[k] ? g->nx : g->ny;
+        int cnt = 1;
+        while (cnt < kFPAngles && k + cnt < np && walk[k + cnt] == walk[k]) {
+            double spread = 0.0;
+            for (int c = 0; c < 4; ++c) {
+                const double nn = (c & 1) ? nc - 1 : 0, ww = (c & 2) ? nw - 1 : 0;
+                double lo = 1e300, hi = -1e300;
+                for (int q = 0; q <= cnt; ++q) {
+                    const double vs = vstar(ang[k + q], nn, ww);
+                    lo = std::min(lo, vs);
+                    hi = std::max(hi, vs);
+                }
+                spread = std::max(spread, hi - lo);
+            }
+            if (spread > kFPSpread) break;
+            ++cnt;
+        }
+        blocks.push_back(FPBlock{k, cnt, walk[k], 0});
+        k += cnt;
+    }
+    // staging shape: the widest stage of any block fits kFPLdsFloats.  The
+    // width is convex in the stage origin (n0, w0), so its maximum over the
+    // launch sits at the extreme origins.
+    const int last_bin_block = ((nc - 1) / kFPBins) * kFPBins;
+    for (int rows = 16; rows >= 1; rows >>= 1) {
+        int need = 0;
+        for (const FPBlock &b : blocks) {
+            const int nw = b.walk ? g->nx : g->ny;
+            const int last_w0 = ((nw - 1) / rows) * rows;
+            for (int c = 0; c < 4; ++c)
+                need = std::max(need, stage_width(ang, b, (c & 1) ? last_bin_block : 0,
+                                                  (c & 2) ? last_w0 : 0, rows));
+        }
+        const int pitch = need | 1;  // odd: column-walk staging writes hit distinct banks
+        if ((int64_t)pitch * rows * sl <= kFPLdsFloats) {
+            *rows_out = rows;
+            *pitch_out = pitch;
+            return XCT_OK;
+        }
+    }
+    return XCT_ETOOBIG;
 }
 
 // ---------------------------------------------------------------- reductions

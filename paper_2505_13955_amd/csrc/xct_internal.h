@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/xct.h"
 
 namespace xct {
@@ -66,16 +68,44 @@ struct FilterArgs {
 };
 hipError_t launch_filter(const FilterArgs &a, int in_t, int out_t, hipStream_t s);
 
+// Forward projector plan.  For each angle the detector coordinate is written
+// as u = A v + B w + u0 (bins), with w the image axis the rays are walked along
+// (rows when |cos| >= |sin|, else columns) and v the other one, so |A| >= |B|.
+struct FPAngle {
+    double A, B, u0;
+    double invA;     // 1 / A
+    float dv;        // -B / A: shift of a bin's crossing per walk step
+    float hw;        // 1 / |A|: half-width of the hat along v
+    float absA;
+    int32_t taps;    // floor(2 hw) + 1 taps cover the hat
+};
+// A run of consecutive angles with the same walk axis whose strips stay close
+// together, projected by one workgroup per bin block.
+struct FPBlock {
+    int32_t k0, count, walk, pad;
+};
+constexpr int kFPAngles = 16;       // angles per block
+constexpr int kFPBins = 256;        // bins per workgroup (one per thread)
+constexpr int kFPLdsFloats = 8192;  // staged image floats per workgroup
+
 struct FPArgs {
     const float *image;  // [S][Ny][Nx]
     float *sino;         // [S][Np][Nc]
-    const double2 *csd;  // [Np] (cos, sin) * pixel / pitch
-    double center;
+    const FPAngle *ang;  // [Np]
+    const FPBlock *blocks;
+    int32_t n_blocks, bin_blocks;
+    int32_t rows;        // walk steps staged at a time (power of two)
+    int32_t pitch;       // LDS floats per staged walk step
     float scale;
     int32_t accumulate;
     int32_t n_angles, n_det, nx, ny, n_slices;
 };
-hipError_t launch_forward(const FPArgs &a, hipStream_t s);
+// Host: angle table, blocks and the LDS shape for `sl` slices per workgroup
+// (XCT_ETOOBIG when no staging shape fits).
+int fp_plan(const xct_geometry *g, std::vector<FPAngle> &ang, std::vector<FPBlock> &blocks, int sl,
+            int *rows, int *pitch);
+// `sl`: slices per workgroup, 1 or 4.
+hipError_t launch_forward(const FPArgs &a, int sl, hipStream_t s);
 
 hipError_t launch_reduce(const float *a, const float *b, int64_t n, double *result,
                          double *partials, int nblocks, int sqdist, hipStream_t s);

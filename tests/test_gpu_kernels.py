@@ -181,26 +181,54 @@ def test_forward_accumulate_and_scale(xct):
 
 # ---------------------------------------------------------------- forward projector
 FP_CASES = [
-    dict(nx=64, ny=64, n_angles=37, n_det=97, det_pitch=1.0, pixel_size=1.0, center=48.0),
-    dict(nx=90, ny=50, n_angles=23, n_det=120, det_pitch=0.7, pixel_size=1.2, center=61.3),
-    dict(nx=1, ny=1, n_angles=5, n_det=3, det_pitch=1.0, pixel_size=1.0, center=1.0),
-    dict(nx=33, ny=129, n_angles=16, n_det=200, det_pitch=1.5, pixel_size=1.0, center=99.5),
+    # random angles (blocks of one or few angles), the two walk axes, both diagonals
+    dict(nx=64, ny=64, n_angles=37, n_det=97, det_pitch=1.0, pixel_size=1.0, center=48.0, angles="rand"),
+    dict(nx=90, ny=50, n_angles=23, n_det=120, det_pitch=0.7, pixel_size=1.2, center=61.3, angles="rand"),
+    dict(nx=1, ny=1, n_angles=5, n_det=3, det_pitch=1.0, pixel_size=1.0, center=1.0, angles="rand"),
+    dict(nx=33, ny=129, n_angles=16, n_det=200, det_pitch=1.5, pixel_size=1.0, center=99.5, angles="rand"),
+    # uniform angles (blocks of many angles), several bin blocks, bins beyond the image
+    dict(nx=48, ny=40, n_angles=90, n_det=600, det_pitch=1.0, pixel_size=1.0, center=300.0, angles="uni"),
+    dict(nx=100, ny=80, n_angles=128, n_det=300, det_pitch=1.0, pixel_size=1.0, center=149.5, angles="uni"),
+    dict(nx=300, ny=300, n_angles=180, n_det=425, det_pitch=1.0, pixel_size=1.0, center=212.0, angles="uni"),
+    # pixels 1/16 of a bin (one walk step per stage, wide strips) and 16 bins wide
+    dict(nx=40, ny=40, n_angles=24, n_det=300, det_pitch=16.0, pixel_size=1.0, center=150.0, angles="uni"),
+    dict(nx=30, ny=30, n_angles=24, n_det=30, det_pitch=1.0, pixel_size=16.0, center=14.5, angles="uni"),
+    # every strip misses the image
+    dict(nx=70, ny=70, n_angles=64, n_det=99, det_pitch=1.0, pixel_size=1.0, center=-150.0, angles="uni"),
 ]
 
 
 @pytest.mark.parametrize("case", range(len(FP_CASES)))
-def test_forward_matches_oracle(xct, case):
+@pytest.mark.parametrize("n_slices", [2, 5])
+def test_forward_matches_oracle(xct, case, n_slices):
     rng = np.random.default_rng(200 + case)
     c = dict(FP_CASES[case])
-    c["angles"] = rng.uniform(0, 2 * math.pi, c["n_angles"])
-    c["angles"][:4] = [0.0, math.pi / 2, math.pi / 4, math.pi][: len(c["angles"][:4])]
+    if c["angles"] == "rand":
+        c["angles"] = rng.uniform(0, 2 * math.pi, c["n_angles"])
+        c["angles"][:4] = [0.0, math.pi / 2, math.pi / 4, math.pi][: len(c["angles"][:4])]
+    else:
+        c["angles"] = synth.uniform_angles(c["n_angles"])
     g = _geom(**c)
-    x = rng.standard_normal((2, g.ny, g.nx))
-    say("fp", case)
+    # two slices: one per workgroup; five: four per workgroup and a partial group
+    x = rng.standard_normal((n_slices, g.ny, g.nx))
+    say("fp", case, n_slices)
     y = xct.forward_project(to_dev(x), g)
     torch.cuda.synchronize()
     ref = oracle.forward(x.astype(np.float32).astype(np.float64), g)
-    assert rel_l2(y.cpu().numpy(), ref) < 2e-5
+    if np.linalg.norm(ref) == 0:
+        assert np.all(y.cpu().numpy() == 0)
+    else:
+        assert rel_l2(y.cpu().numpy(), ref) < 2e-5
+
+
+def test_forward_is_deterministic(xct):
+    rng = np.random.default_rng(15)
+    g = _geom(n_angles=200, n_det=450, nx=300, ny=260, center=230.7)
+    x = to_dev(rng.standard_normal((3, 260, 300)))
+    a = xct.forward_project(x, g)
+    b = xct.forward_project(x, g)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
 
 
 def test_adjoint_identity_fp64(xct):
