@@ -58,7 +58,8 @@ typedef enum {
     XCT_EHIP = -5        /* the HIP runtime reported an error */
 } xct_status;
 
-typedef enum { XCT_F32 = 0, XCT_F16 = 1, XCT_BF16 = 2 } xct_dtype;
+/* XCT_U16: raw detector counts, accepted only by xct_preprocess_filter. */
+typedef enum { XCT_F32 = 0, XCT_F16 = 1, XCT_BF16 = 2, XCT_U16 = 3 } xct_dtype;
 
 /* Filter windows W(nu) applied to the ramp |nu| on |nu| <= 1/2 (cut-off at
  * the detector Nyquist frequency).  The spatial kernels are the inverse DTFTs
@@ -96,6 +97,29 @@ typedef struct {
 int xct_filter(const xct_geometry *g, int32_t n_slices, const void *sino, int32_t sino_t,
                void *filtered, int32_t filtered_t, int32_t window, xct_stream stream);
 
+/* Pre-processing front end fused into the filter (Section V-A c, stage 2:
+ * Beer-Lambert conversion, Gaussian blur, then filtering), which also regroups
+ * the projection stack as acquired into one sinogram per detector row:
+ *   p[s][k][n]  = -ln(max(I - D, floor) / max(F - D, floor)),
+ *                 I = proj[k][row_begin + s][n], D = dark[row_begin + s][n],
+ *                 F = flat[row_begin + s][n]                      (FP32 logf)
+ *   b[s][k][n]  = sum_{|m| <= R} g[m] p[s][k][clamp(n + m, 0, N_c - 1)],
+ *                 g[m] = exp(-m^2 / (2 sigma^2)) / sum, R = int(4 sigma + 0.5)
+ *                 (sigma = 0: b = p)
+ *   filtered    = xct_filter of b with the same window.
+ *   proj       device [N_p][n_rows][N_c] of proj_t (XCT_U16 counts or XCT_F32)
+ *   dark, flat device [n_rows][N_c] FP32 (dark current and open-beam fields)
+ *   filtered   device [n_slices][N_p][N_c] of filtered_t (F32 / F16 / BF16);
+ *              must not overlap proj
+ * Rows row_begin .. row_begin + n_slices - 1 of the detector are processed
+ * (a slab of the scan).  Errors: XCT_EINVAL for null pointers, a row range
+ * outside [0, n_rows), floor <= 0, sigma < 0 or non-finite; XCT_ETOOBIG for
+ * R > 64 (sigma >= 16.125) or N_c > 8192; XCT_EDTYPE for other dtypes. */
+int xct_preprocess_filter(const xct_geometry *g, int32_t n_rows, int32_t row_begin, int32_t n_slices,
+                          const void *proj, int32_t proj_t, const float *dark, const float *flat,
+                          float floor, float blur_sigma, void *filtered, int32_t filtered_t,
+                          int32_t window, xct_stream stream);
+
 /* Back-projection (Section IV-B, second step) and the adjoint of the forward
  * projector:
  *   image[s][i][j] = (accumulate ? image[s][i][j] : 0)
@@ -105,6 +129,24 @@ int xct_filter(const xct_geometry *g, int32_t n_slices, const void *sino, int32_
  * the exact transpose of xct_forward_project uses scale = pixel^2 / pitch. */
 int xct_backproject(const xct_geometry *g, int32_t n_slices, const void *sino, int32_t sino_t,
                     float *image, float scale, int32_t accumulate, xct_stream stream);
+
+/* Back-projection with the volume-storage epilogue of the reconstruction
+ * pipeline (Section V-A c, stage 4: slices normalised by a CT-number range and
+ * quantised to 16-bit unsigned integers).  Each voxel's attenuation
+ *   mu = scale * (A^T sino)      (FP32, as xct_backproject computes it)
+ * becomes the CT number HU = 1000 (mu - mu_water) / mu_water, and the range
+ * [hu_min, hu_max] maps linearly onto the codes [0, 65535]:
+ *   code = clamp(rint(fl(fl(mu * a) + b)), 0, 65535)
+ * with a = fl32(1000 / mu_water * S), b = fl32((-1000 - hu_min) * S),
+ * S = 65535 / (hu_max - hu_min) evaluated in FP64 in that order; fl() is one
+ * FP32 rounding, rint rounds half to even, and NaN gives 0.
+ *   image    device [n_slices][N_y][N_x] uint16, overwritten (half the bytes
+ *            of the FP32 image)
+ * Errors: XCT_EINVAL for mu_water <= 0, hu_max <= hu_min, non-finite
+ * arguments or a, b that overflow FP32; otherwise as xct_backproject. */
+int xct_backproject_u16(const xct_geometry *g, int32_t n_slices, const void *sino, int32_t sino_t,
+                        uint16_t *image, float scale, double mu_water, double hu_min, double hu_max,
+                        xct_stream stream);
 
 /* Pixel-driven forward projector, the exact transpose of the back-projector:
  *   sino[s][k][n] = (accumulate ? sino[s][k][n] : 0)

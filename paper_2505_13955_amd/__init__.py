@@ -13,6 +13,7 @@ from .xct import (  # noqa: F401
     XCT_BF16,
     XCT_F16,
     XCT_F32,
+    XCT_U16,
     XctError,
     adjoint_scale,
     backproject,
@@ -23,12 +24,14 @@ from .xct import (  # noqa: F401
     load_library,
     make_geometry,
     xct_backproject,
+    xct_backproject_u16,
     xct_cache_clear,
     xct_dot_f64,
     xct_fbp_batch,
     xct_fbp_workspace_bytes,
     xct_filter,
     xct_forward_project,
+    xct_preprocess_filter,
     xct_sqdist_f64,
     xct_version,
 )

@@ -81,6 +81,7 @@ std::mutex g_mu;
 std::unordered_map<std::string, GeoTables> g_geo;
 std::unordered_map<std::string, FilterTables> g_filt;
 std::unordered_map<std::string, FPTables> g_fp;
+std::unordered_map<std::string, float *> g_blur;
 
 template <typename T>
 void key_append(std::string &k, const T &v)
@@ -131,6 +132,42 @@ int geo_tables(const xct_geometry *g, GeoTables *out)
     }
     g_geo.emplace(key, t);
     *out = t;
+    return XCT_OK;
+}
+
+// Unit-sum sampled Gaussian of standard deviation sigma over -R..R,
+// R = int(4 sigma + 0.5), in FP64 rounded once to FP32, cached on the device.
+int blur_taps(float sigma, int radius, const float **out)
+{
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    std::string key;
+    key_append(key, dev);
+    key_append(key, sigma);
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_blur.find(key);
+    if (it != g_blur.end()) {
+        *out = it->second;
+        return XCT_OK;
+    }
+    std::vector<double> g(2 * radius + 1);
+    double sum = 0.0;
+    for (int m = -radius; m <= radius; ++m) {
+        const double t = (double)m / (double)sigma;
+        g[m + radius] = std::exp(-0.5 * t * t);
+        sum += g[m + radius];
+    }
+    std::vector<float> g32(g.size());
+    for (size_t i = 0; i < g.size(); ++i) g32[i] = (float)(g[i] / sum);
+    float *d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(float) * g32.size());
+    if (e == hipSuccess) e = hipMemcpy(d, g32.data(), sizeof(float) * g32.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (d) (void)hipFree(d);
+        return hip_fail(e);
+    }
+    g_blur.emplace(key, d);
+    *out = d;
     return XCT_OK;
 }
 
@@ -313,10 +350,12 @@ struct BPJob {
     GeoTables t;
     int32_t n_slices;
     const void *sino;
-    float *image;
+    void *image;
     float scale;
     int32_t accumulate;
     int path;
+    int32_t out_u16 = 0;
+    float code_a = 0.0f, code_b = 0.0f;
 };
 
 // Tiles per slice as the kernel indexes them (tiles_x, tiles_y) and the work
@@ -384,6 +423,9 @@ int launch_bp_jobs(std::vector<BPJob> jobs, int dtype, unsigned int *counter, hi
         sl.mirror = path != kPathGeneric ? (int32_t)std::nearbyint(2.0 * j.g->center) : 0;
         sl.scale = j.scale;
         sl.accumulate = j.accumulate;
+        sl.out_u16 = j.out_u16;
+        sl.code_a = j.code_a;
+        sl.code_b = j.code_b;
         items += n_items;
         W = std::max(W, window_entries(j.g->pixel_size / j.g->det_pitch));
     }
@@ -456,9 +498,11 @@ void xct_cache_clear(void)
         (void)hipFree(kv.second.ang);
         (void)hipFree(kv.second.blocks);
     }
+    for (auto &kv : g_blur) (void)hipFree(kv.second);
     g_geo.clear();
     g_filt.clear();
     g_fp.clear();
+    g_blur.clear();
 }
 
 int xct_filter(const xct_geometry *g, int32_t n_slices, const void *sino, int32_t sino_t,
@@ -474,7 +518,7 @@ int xct_filter(const xct_geometry *g, int32_t n_slices, const void *sino, int32_
     FilterTables ft;
     int L, lg;
     if (int rc = filter_tables(g->n_det, window, g->det_pitch, &ft, &L, &lg)) return rc;
-    FilterArgs a;
+    FilterArgs a{};
     a.in = sino;
     a.out = filtered;
     a.tw = ft.tw;
@@ -484,6 +528,54 @@ int xct_filter(const xct_geometry *g, int32_t n_slices, const void *sino, int32_
     a.L = L;
     a.log2L = lg;
     hipError_t e = launch_filter(a, sino_t, filtered_t, (hipStream_t)stream);
+    return e == hipSuccess ? XCT_OK : hip_fail(e);
+}
+
+int xct_preprocess_filter(const xct_geometry *g, int32_t n_rows, int32_t row_begin, int32_t n_slices,
+                          const void *proj, int32_t proj_t, const float *dark, const float *flat,
+                          float floor, float blur_sigma, void *filtered, int32_t filtered_t,
+                          int32_t window, xct_stream stream)
+{
+    if (int rc = check_geometry(g, false)) return rc;
+    if (int rc = check_slices(g, n_slices)) return rc;
+    if (n_rows < 1 || row_begin < 0 || (int64_t)row_begin + n_slices > n_rows) return XCT_EINVAL;
+    if (!proj || !dark || !flat || !filtered) return XCT_EINVAL;
+    if ((proj_t != XCT_U16 && proj_t != XCT_F32) || !dtype_ok(filtered_t)) return XCT_EDTYPE;
+    if (window < XCT_RAM_LAK || window > XCT_HANN) return XCT_EDTYPE;
+    if (!std::isfinite(floor) || !(floor > 0.0f)) return XCT_EINVAL;
+    if (!std::isfinite(blur_sigma) || blur_sigma < 0.0f) return XCT_EINVAL;
+    if (g->n_det > kMaxFFT / 2) return XCT_ETOOBIG;
+    const int radius = blur_sigma == 0.0f ? 0 : (int)(4.0 * (double)blur_sigma + 0.5);
+    if (radius > 64) return XCT_ETOOBIG;
+    // the output must not overlap the projection stack
+    const char *pb = static_cast<const char *>(proj), *fb = static_cast<const char *>(filtered);
+    const size_t pbytes = (size_t)g->n_angles * n_rows * g->n_det * dtype_size(proj_t);
+    const size_t fbytes = (size_t)n_slices * g->n_angles * g->n_det * dtype_size(filtered_t);
+    if (pb < fb + fbytes && fb < pb + pbytes) return XCT_EINVAL;
+    FilterTables ft;
+    int L, lg;
+    if (int rc = filter_tables(g->n_det, window, g->det_pitch, &ft, &L, &lg)) return rc;
+    const float *taps = nullptr;
+    if (radius > 0)
+        if (int rc = blur_taps(blur_sigma, radius, &taps)) return rc;
+    FilterArgs a{};
+    a.in = proj;
+    a.out = filtered;
+    a.tw = ft.tw;
+    a.H = ft.H;
+    a.rows = (int64_t)n_slices * g->n_angles;
+    a.nc = g->n_det;
+    a.L = L;
+    a.log2L = lg;
+    a.pre.dark = dark;
+    a.pre.flat = flat;
+    a.pre.taps = taps;
+    a.pre.radius = radius;
+    a.pre.n_rows = n_rows;
+    a.pre.row_begin = row_begin;
+    a.pre.n_angles = g->n_angles;
+    a.pre.floor = floor;
+    hipError_t e = launch_front_end_filter(a, proj_t, filtered_t, (hipStream_t)stream);
     return e == hipSuccess ? XCT_OK : hip_fail(e);
 }
 
@@ -503,6 +595,38 @@ int xct_backproject(const xct_geometry *g, int32_t n_slices, const void *sino, i
     j.scale = scale;
     j.accumulate = accumulate ? 1 : 0;
     j.path = choose_path(g);
+    if (int rc = geo_tables(g, &j.t)) return rc;
+    return launch_bp_jobs({j}, sino_t, nullptr, (hipStream_t)stream);
+}
+
+int xct_backproject_u16(const xct_geometry *g, int32_t n_slices, const void *sino, int32_t sino_t,
+                        uint16_t *image, float scale, double mu_water, double hu_min, double hu_max,
+                        xct_stream stream)
+{
+    if (int rc = check_geometry(g, true)) return rc;
+    if (int rc = check_slices(g, n_slices)) return rc;
+    if (!sino || !image) return XCT_EINVAL;
+    if (!dtype_ok(sino_t)) return XCT_EDTYPE;
+    if (!std::isfinite(scale) || !std::isfinite(mu_water) || !std::isfinite(hu_min) ||
+        !std::isfinite(hu_max) || !(mu_water > 0.0) || !(hu_max > hu_min))
+        return XCT_EINVAL;
+    // code = A mu + B: HU = 1000 (mu - mu_water) / mu_water, [hu_min, hu_max] -> [0, 65535]
+    const double span = 65535.0 / (hu_max - hu_min);
+    const double A = 1000.0 / mu_water * span;
+    const double B = (-1000.0 - hu_min) * span;
+    const float a32 = (float)A, b32 = (float)B;
+    if (!std::isfinite(a32) || !std::isfinite(b32)) return XCT_EINVAL;
+    BPJob j;
+    j.g = g;
+    j.n_slices = n_slices;
+    j.sino = sino;
+    j.image = image;
+    j.scale = scale;
+    j.accumulate = 0;
+    j.path = choose_path(g);
+    j.out_u16 = 1;
+    j.code_a = a32;
+    j.code_b = b32;
     if (int rc = geo_tables(g, &j.t)) return rc;
     return launch_bp_jobs({j}, sino_t, nullptr, (hipStream_t)stream);
 }

@@ -87,6 +87,28 @@ __device__ __forceinline__ void select_slab(KBatch *b, int s, BPSlab &out)
     out.mirror = b->slab[s].mirror;
     out.scale = b->slab[s].scale;
     out.accumulate = b->slab[s].accumulate;
+    out.out_u16 = b->slab[s].out_u16;
+    out.code_a = b->slab[s].code_a;
+    out.code_b = b->slab[s].code_b;
+}
+
+// Store of voxel `idx` (slab-wide index) from its accumulated sum: v = scale
+// * acc in FP32 (added to the stored value when accumulating), or the CT-number
+// code of v: the affine map fl(fl(v a) + b) rounded to the nearest integer,
+// ties to even, and clamped to [0, 65535] (NaN gives 0).  The explicit
+// roundings keep the code independent of FMA contraction.
+__device__ __forceinline__ void store_voxel(const BPSlab &sl, int64_t idx, float acc)
+{
+    float v = sl.scale * acc;
+    if (sl.out_u16) {
+        const float t = __fadd_rn(__fmul_rn(v, sl.code_a), sl.code_b);
+        const float c = fminf(fmaxf(rintf(t), 0.0f), 65535.0f);
+        static_cast<uint16_t *>(sl.image)[idx] = (uint16_t)c;
+    } else {
+        float *img = static_cast<float *>(sl.image);
+        if (sl.accumulate) v += img[idx];
+        img[idx] = v;
+    }
 }
 
 __device__ __forceinline__ int find_slab(KBatch *b, int64_t item)
@@ -218,18 +240,13 @@ __global__ __launch_bounds__(kBPThreads) void bp_generic_kernel(BPBatch arg)
             }
         }
 
-        float *img = sl.image + (int64_t)z * sl.nx * sl.ny;
+        const int64_t plane = (int64_t)z * sl.nx * sl.ny;
 #pragma unroll
         for (int bb = 0; bb < 4; ++bb) {
 #pragma unroll
             for (int aa = 0; aa < 4; ++aa) {
                 const int i = i0 + py + 16 * bb, j = j0 + px + 16 * aa;
-                if (i < sl.ny && j < sl.nx) {
-                    const int64_t idx = (int64_t)i * sl.nx + j;
-                    float v = sl.scale * acc[bb * 4 + aa];
-                    if (sl.accumulate) v += img[idx];
-                    img[idx] = v;
-                }
+                if (i < sl.ny && j < sl.nx) store_voxel(sl, plane + (int64_t)i * sl.nx + j, acc[bb * 4 + aa]);
             }
         }
     }
@@ -432,7 +449,7 @@ __global__ __launch_bounds__(kBPThreads * SL, 4) void bp_sym_kernel(BPBatch arg)
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
             if (s >= nsl) break;
-            float *img = sl.image + (int64_t)(z0 + s) * N * N;
+            const int64_t plane = (int64_t)(z0 + s) * N * N;
 #pragma unroll
             for (int cc = 0; cc < ROWS; ++cc) {
 #pragma unroll
@@ -445,11 +462,7 @@ __global__ __launch_bounds__(kBPThreads * SL, 4) void bp_sym_kernel(BPBatch arg)
                                                 (int64_t)(N - 1 - i) * N + (N - 1 - j),
                                                 (int64_t)j * N + (N - 1 - i)};
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            float v = sl.scale * acc[s][r][pi];
-                            if (sl.accumulate) v += img[idx[r]];
-                            img[idx[r]] = v;
-                        }
+                        for (int r = 0; r < 4; ++r) store_voxel(sl, plane + idx[r], acc[s][r][pi]);
                     }
                 }
             }

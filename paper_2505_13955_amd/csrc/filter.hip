@@ -33,6 +33,8 @@ __device__ __forceinline__ float ld_in<bf16_t>(const bf16_t *p, int64_t i)
 {
     return __uint_as_float((uint32_t)p[i].bits << 16);
 }
+template <>
+__device__ __forceinline__ float ld_in<uint16_t>(const uint16_t *p, int64_t i) { return (float)p[i]; }
 
 template <typename T>
 __device__ __forceinline__ void st_out(T *p, int64_t i, float v);
@@ -136,7 +138,61 @@ __device__ __forceinline__ void fft_forward(float2 *z, int L, int log2L, const f
     for (; Ns < L; Ns <<= 2) pass_r4(z, L, Ns, tw, tid, nt);
 }
 
-template <typename TI, typename TO>
+// Line integral of one raw detector sample (Beer-Lambert, Section V-A c
+// stage 2): -ln((I - D) / (F - D)), both differences clamped below at `floor`.
+__device__ __forceinline__ float beer_lambert(float i, float d, float f, float floor)
+{
+    return -logf(fmaxf(i - d, floor) / fmaxf(f - d, floor));
+}
+
+// Front end of a row pair: rows r0, r0 + 1 of the output are detector row
+// row_begin + s of projection k (r = s N_p + k), read from the projection
+// stack [N_p][n_rows][N_c] with the dark and flat fields of that detector
+// row.  The line integrals are blurred along the channels with the sampled
+// Gaussian (edge samples replicated) staged in the upper half of z, which is
+// zero padding of the transform and holds N_c <= L/2 values.
+template <typename TI>
+__device__ __forceinline__ void load_front_end(float2 *z, const FilterArgs &a, int64_t r0, bool has1,
+                                               int tid, int nt)
+{
+    const int L = a.L, nc = a.nc;
+    const PreArgs &pre = a.pre;
+    const TI *src[2];
+    const float *drow[2], *frow[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int64_t r = has1 || h == 0 ? r0 + h : r0;
+        const int64_t s = r / pre.n_angles, k = r - s * pre.n_angles;
+        const int64_t det_row = pre.row_begin + s;
+        src[h] = static_cast<const TI *>(a.in) + (k * pre.n_rows + det_row) * nc;
+        drow[h] = pre.dark + det_row * nc;
+        frow[h] = pre.flat + det_row * nc;
+    }
+    float2 *stage = pre.radius > 0 ? z + (L >> 1) : z;
+    for (int n = tid; n < nc; n += nt) {
+        const float p0 = beer_lambert(ld_in(src[0], n), drow[0][n], frow[0][n], pre.floor);
+        const float p1 = has1 ? beer_lambert(ld_in(src[1], n), drow[1][n], frow[1][n], pre.floor) : 0.0f;
+        stage[n] = make_float2(p0, p1);
+    }
+    if (pre.radius > 0) {
+        __syncthreads();
+        const int R = pre.radius;
+        for (int n = tid; n < nc; n += nt) {
+            float b0 = 0.0f, b1 = 0.0f;
+            for (int m = -R; m <= R; ++m) {
+                const float g = pre.taps[m + R];
+                const float2 v = stage[min(max(n + m, 0), nc - 1)];
+                b0 = fmaf(g, v.x, b0);
+                b1 = fmaf(g, v.y, b1);
+            }
+            z[n] = make_float2(b0, b1);
+        }
+        __syncthreads();
+    }
+    for (int n = nc + tid; n < L; n += nt) z[n] = make_float2(0.0f, 0.0f);
+}
+
+template <typename TI, typename TO, bool PRE>
 __global__ __launch_bounds__(1024) void filter_kernel(FilterArgs a)
 {
     extern __shared__ float2 z[];
@@ -144,16 +200,20 @@ __global__ __launch_bounds__(1024) void filter_kernel(FilterArgs a)
     const int L = a.L, nc = a.nc;
     const int64_t r0 = (int64_t)blockIdx.x * 2;
     const bool has1 = r0 + 1 < a.rows;
-    const TI *p0 = static_cast<const TI *>(a.in) + r0 * nc;
-    const TI *p1 = p0 + nc;
 
-    for (int n = tid; n < L; n += nt) {
-        float x0 = 0.0f, x1 = 0.0f;
-        if (n < nc) {
-            x0 = ld_in(p0, n);
-            if (has1) x1 = ld_in(p1, n);
+    if (PRE) {
+        load_front_end<TI>(z, a, r0, has1, tid, nt);
+    } else {
+        const TI *p0 = static_cast<const TI *>(a.in) + r0 * nc;
+        const TI *p1 = p0 + nc;
+        for (int n = tid; n < L; n += nt) {
+            float x0 = 0.0f, x1 = 0.0f;
+            if (n < nc) {
+                x0 = ld_in(p0, n);
+                if (has1) x1 = ld_in(p1, n);
+            }
+            z[n] = make_float2(x0, x1);
         }
-        z[n] = make_float2(x0, x1);
     }
     __syncthreads();
     fft_forward(z, L, a.log2L, a.tw, tid, nt);
@@ -174,35 +234,41 @@ __global__ __launch_bounds__(1024) void filter_kernel(FilterArgs a)
     }
 }
 
-template <typename TI, typename TO>
+template <typename TI, typename TO, bool PRE>
 static hipError_t launch_typed(const FilterArgs &a, hipStream_t s)
 {
     const int nt = max(64, min(1024, a.L / 16));
     const size_t lds = (size_t)a.L * sizeof(float2);
     (void)hipGetLastError();  // report only what this launch does
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(filter_kernel<TI, TO>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(filter_kernel<TI, TO, PRE>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     const int64_t pairs = (a.rows + 1) / 2;
-    hipLaunchKernelGGL((filter_kernel<TI, TO>), dim3((unsigned)pairs), dim3(nt), lds, s, a);
+    hipLaunchKernelGGL((filter_kernel<TI, TO, PRE>), dim3((unsigned)pairs), dim3(nt), lds, s, a);
     return hipGetLastError();
 }
 
-template <typename TI>
+template <typename TI, bool PRE>
 static hipError_t launch_out(const FilterArgs &a, int out_t, hipStream_t s)
 {
-    if (out_t == XCT_F32) return launch_typed<TI, float>(a, s);
-    if (out_t == XCT_F16) return launch_typed<TI, f16_t>(a, s);
-    return launch_typed<TI, bf16_t>(a, s);
+    if (out_t == XCT_F32) return launch_typed<TI, float, PRE>(a, s);
+    if (out_t == XCT_F16) return launch_typed<TI, f16_t, PRE>(a, s);
+    return launch_typed<TI, bf16_t, PRE>(a, s);
 }
 
 hipError_t launch_filter(const FilterArgs &a, int in_t, int out_t, hipStream_t s)
 {
-    if (in_t == XCT_F32) return launch_out<float>(a, out_t, s);
-    if (in_t == XCT_F16) return launch_out<f16_t>(a, out_t, s);
-    return launch_out<bf16_t>(a, out_t, s);
+    if (in_t == XCT_F32) return launch_out<float, false>(a, out_t, s);
+    if (in_t == XCT_F16) return launch_out<f16_t, false>(a, out_t, s);
+    return launch_out<bf16_t, false>(a, out_t, s);
+}
+
+hipError_t launch_front_end_filter(const FilterArgs &a, int in_t, int out_t, hipStream_t s)
+{
+    if (in_t == XCT_U16) return launch_out<uint16_t, true>(a, out_t, s);
+    return launch_out<float, true>(a, out_t, s);
 }
 
 }  // namespace xct

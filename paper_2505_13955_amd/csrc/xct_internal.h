@@ -22,7 +22,7 @@ typedef _Float16 f16_t;
 // One slab of slices as seen by the back-projection kernels.
 struct BPSlab {
     const void *sino;    // [S][Np][Nc] filtered rows (dtype of the launch)
-    float *image;        // [S][Ny][Nx]
+    void *image;         // [S][Ny][Nx], FP32 or (out_u16) uint16 CT-number codes
     const float2 *cs;    // [Np] (cos, sin) * pixel / pitch, FP32
     const double2 *csd;  // [Np] the same in FP64 (window anchors)
     double center;       // c, in bins
@@ -33,6 +33,8 @@ struct BPSlab {
     int32_t mirror;            // 2c, an integer on the symmetric path
     float scale;
     int32_t accumulate;
+    int32_t out_u16;           // store clamp(rint(fl(fl(v code_a) + code_b))) as uint16
+    float code_a, code_b;
 };
 
 struct BPBatch {
@@ -56,8 +58,18 @@ size_t bp_sym_lds_bytes(int win, int kb, int sl);
 int bp_sym_window(int need);  // window of the symmetric kernel covering `need` (0: none)
 int bp_max_blocks_per_cu(int path, int dtype, int win, int sl, size_t lds);
 
+// Front end read in the filter's load phase: raw projection stack
+// [n_angles][n_rows][Nc] with dark and flat fields [n_rows][Nc].
+struct PreArgs {
+    const float *dark, *flat;
+    const float *taps;   // [2 radius + 1] unit-sum Gaussian (radius 0: no blur)
+    int32_t radius;
+    int32_t n_rows, row_begin, n_angles;
+    float floor;
+};
+
 struct FilterArgs {
-    const void *in;    // [rows][Nc]
+    const void *in;    // [rows][Nc] (front end: the projection stack)
     void *out;         // [rows][Nc]
     const float2 *tw;  // [L] exp(-2 pi i e / L)
     const float *H;    // [L] real spectrum / (L * pitch)
@@ -65,8 +77,10 @@ struct FilterArgs {
     int32_t nc;
     int32_t L;
     int32_t log2L;
+    PreArgs pre;
 };
 hipError_t launch_filter(const FilterArgs &a, int in_t, int out_t, hipStream_t s);
+hipError_t launch_front_end_filter(const FilterArgs &a, int in_t, int out_t, hipStream_t s);
 
 // Forward projector plan.  For each angle the detector coordinate is written
 // as u = A v + B w + u0 (bins), with w the image axis the rays are walked along

@@ -24,7 +24,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libxct.so")
 
-XCT_F32, XCT_F16, XCT_BF16 = 0, 1, 2
+XCT_F32, XCT_F16, XCT_BF16, XCT_U16 = 0, 1, 2, 3
 WINDOWS = {"ram_lak": 0, "shepp_logan": 1, "hann": 2}
 DTYPES = {torch.float32: XCT_F32, torch.float16: XCT_F16, torch.bfloat16: XCT_BF16}
 TORCH_DTYPES = {v: k for k, v in DTYPES.items()}
@@ -61,7 +61,9 @@ class XctSlab(ctypes.Structure):
 
 EXPORTS = (
     "xct_filter",
+    "xct_preprocess_filter",
     "xct_backproject",
+    "xct_backproject_u16",
     "xct_forward_project",
     "xct_fbp_workspace_bytes",
     "xct_fbp_batch",
@@ -91,7 +93,11 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
     sp = ctypes.POINTER(XctSlab)
     sig = {
         "xct_filter": ([gp, i32, vp, i32, vp, i32, i32, vp], ctypes.c_int),
+        "xct_preprocess_filter": ([gp, i32, i32, i32, vp, i32, vp, vp, ctypes.c_float, ctypes.c_float,
+                                   vp, i32, i32, vp], ctypes.c_int),
         "xct_backproject": ([gp, i32, vp, i32, vp, ctypes.c_float, i32, vp], ctypes.c_int),
+        "xct_backproject_u16": ([gp, i32, vp, i32, vp, ctypes.c_float, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_double, vp], ctypes.c_int),
         "xct_forward_project": ([gp, i32, vp, vp, ctypes.c_float, i32, vp], ctypes.c_int),
         "xct_fbp_workspace_bytes": ([sp, i32, i32], sz),
         "xct_fbp_batch": ([sp, i32, i32, i32, i32, vp, sz, vp], ctypes.c_int),
@@ -167,6 +173,30 @@ def xct_filter(geom, sino: torch.Tensor, filtered: torch.Tensor, window: str) ->
     _check("xct_filter", rc)
 
 
+def xct_preprocess_filter(geom, proj: torch.Tensor, dark: torch.Tensor, flat: torch.Tensor,
+                          row_begin: int, filtered: torch.Tensor, window: str, floor: float = 1.0,
+                          blur_sigma: float = 0.0) -> None:
+    """filtered[s] = ramp filter of the blurred Beer-Lambert line integrals of
+    detector row row_begin + s, from the raw projection stack proj
+    [N_p][N_r][N_c] (uint16 counts or float32) and the dark / flat fields
+    [N_r][N_c]; filtered is [S][N_p][N_c]."""
+    lib = load_library()
+    if proj.dim() != 3 or proj.shape[0] != geom.n_angles or proj.shape[2] != geom.n_det:
+        raise ValueError(f"proj must be (N_p, N_r, N_c) = ({geom.n_angles}, *, {geom.n_det})")
+    n_rows = proj.shape[1]
+    S = _slices(filtered, geom, False)
+    p_in = _dev(proj, "proj", (torch.uint16, torch.float32))
+    p_d = _dev(dark, "dark", (torch.float32,), (n_rows, geom.n_det))
+    p_f = _dev(flat, "flat", (torch.float32,), (n_rows, geom.n_det))
+    p_out = _dev(filtered, "filtered", DTYPES)
+    g, ang = make_geometry(geom)
+    pt = XCT_U16 if proj.dtype == torch.uint16 else XCT_F32
+    rc = lib.xct_preprocess_filter(ctypes.byref(g), n_rows, int(row_begin), S, p_in, pt, p_d, p_f,
+                                   float(floor), float(blur_sigma), p_out, DTYPES[filtered.dtype],
+                                   WINDOWS[window], _stream(proj))
+    _check("xct_preprocess_filter", rc)
+
+
 def xct_backproject(geom, sino: torch.Tensor, image: torch.Tensor, scale: float,
                     accumulate: bool = False) -> None:
     """image = (accumulate ? image : 0) + scale * A^T sino."""
@@ -178,6 +208,20 @@ def xct_backproject(geom, sino: torch.Tensor, image: torch.Tensor, scale: float,
     rc = lib.xct_backproject(ctypes.byref(g), S, p_in, DTYPES[sino.dtype], p_out, float(scale),
                              1 if accumulate else 0, _stream(sino))
     _check("xct_backproject", rc)
+
+
+def xct_backproject_u16(geom, sino: torch.Tensor, image: torch.Tensor, scale: float,
+                        mu_water: float, hu_min: float, hu_max: float) -> None:
+    """image (uint16) = CT-number codes of scale * A^T sino: HU = 1000 (mu -
+    mu_water) / mu_water, [hu_min, hu_max] mapped onto [0, 65535]."""
+    lib = load_library()
+    S = _slices(sino, geom, False)
+    p_in = _dev(sino, "sino", DTYPES)
+    p_out = _dev(image, "image", (torch.uint16,), (S, geom.ny, geom.nx))
+    g, ang = make_geometry(geom)
+    rc = lib.xct_backproject_u16(ctypes.byref(g), S, p_in, DTYPES[sino.dtype], p_out, float(scale),
+                                 float(mu_water), float(hu_min), float(hu_max), _stream(sino))
+    _check("xct_backproject_u16", rc)
 
 
 def xct_forward_project(geom, image: torch.Tensor, sino: torch.Tensor, scale: float | None = None,

@@ -2,7 +2,7 @@
 
 This package only *describes and generates* inputs: scan geometries, random
 ellipse phantoms, their closed-form parallel-beam line integrals, noise and the
-FP16/BF16 storage encoding.  It contains none of the reconstruction arithmetic
+FP16/BF16 storage encoding, and raw detector counts with dark and flat fields.  It contains none of the reconstruction arithmetic
 (no filtering, no back-projection, no pixel-driven projector); the FP64 oracle
 and the HIP library each implement those on their own.
 """
@@ -20,6 +20,7 @@ from .phantom import (
     encode_storage,
     decode_storage,
 )
+from .detector import detector_fields, attenuation_scale, raw_counts
 from . import configs
 
 __all__ = [
@@ -35,5 +36,8 @@ __all__ = [
     "add_poisson_noise",
     "encode_storage",
     "decode_storage",
+    "detector_fields",
+    "attenuation_scale",
+    "raw_counts",
     "configs",
 ]

@@ -16,6 +16,7 @@ from paper_2505_13955_amd import xct as X
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 EINVAL, EDTYPE, EWORKSPACE, ETOOBIG = -1, -2, -3, -4
 FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation
+FAKE2 = ctypes.c_void_p(0x7F0000000000)  # a second such pointer, far from the first
 
 
 def header_functions():
@@ -98,6 +99,46 @@ def test_backproject_validation(lib):
     assert lib.xct_backproject(None, 1, FAKE, 0, FAKE, 1.0, 0, None) == EINVAL
     assert lib.xct_forward_project(ctypes.byref(g), 70000, FAKE, FAKE, 1.0, 0, None) == ETOOBIG
     assert lib.xct_forward_project(ctypes.byref(g), 1, FAKE, FAKE, float("inf"), 0, None) == EINVAL
+
+
+def test_preprocess_filter_validation(lib):
+    g, _ = _geom()
+    f = lib.xct_preprocess_filter
+    ok = dict(n_rows=4, row_begin=1, n_slices=2, proj_t=3, floor=1.0, sigma=1.0, out_t=0, window=0)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return f(ctypes.byref(g), a["n_rows"], a["row_begin"], a["n_slices"], FAKE, a["proj_t"], FAKE,
+                 FAKE, a["floor"], a["sigma"], FAKE2, a["out_t"], a["window"], None)
+
+    assert call(row_begin=3) == EINVAL              # rows 3, 4 of 4
+    assert call(row_begin=-1) == EINVAL
+    assert call(n_rows=0) == EINVAL
+    assert call(n_slices=0) == EINVAL
+    assert call(floor=0.0) == EINVAL
+    assert call(floor=float("nan")) == EINVAL
+    assert call(sigma=-0.5) == EINVAL
+    assert call(sigma=float("inf")) == EINVAL
+    assert call(sigma=16.125) == ETOOBIG             # blur radius int(65.0) > 64
+    assert call(proj_t=1) == EDTYPE                  # FP16 counts are not accepted
+    assert call(out_t=3) == EDTYPE
+    assert call(window=5) == EDTYPE
+    assert f(ctypes.byref(g), 4, 1, 2, None, 3, FAKE, FAKE, 1.0, 1.0, FAKE2, 0, 0, None) == EINVAL
+    # the output may not overlap the projection stack
+    assert f(ctypes.byref(g), 4, 1, 2, FAKE, 3, FAKE, FAKE, 1.0, 1.0, FAKE, 0, 0, None) == EINVAL
+
+
+def test_backproject_u16_validation(lib):
+    g, _ = _geom()
+    f = lib.xct_backproject_u16
+    assert f(ctypes.byref(g), 1, FAKE, 0, FAKE, 1.0, 0.0, -1000.0, 3000.0, None) == EINVAL  # mu_water
+    assert f(ctypes.byref(g), 1, FAKE, 0, FAKE, 1.0, -0.2, -1000.0, 3000.0, None) == EINVAL
+    assert f(ctypes.byref(g), 1, FAKE, 0, FAKE, 1.0, 0.2, 3000.0, 3000.0, None) == EINVAL  # empty range
+    assert f(ctypes.byref(g), 1, FAKE, 0, FAKE, 1.0, 0.2, float("nan"), 3000.0, None) == EINVAL
+    assert f(ctypes.byref(g), 1, FAKE, 0, FAKE, float("inf"), 0.2, -1000.0, 3000.0, None) == EINVAL
+    assert f(ctypes.byref(g), 1, FAKE, 0, FAKE, 1.0, 1e-300, -1000.0, 3000.0, None) == EINVAL  # a overflows
+    assert f(ctypes.byref(g), 1, FAKE, 7, FAKE, 1.0, 0.2, -1000.0, 3000.0, None) == EDTYPE
+    assert f(ctypes.byref(g), 1, None, 0, FAKE, 1.0, 0.2, -1000.0, 3000.0, None) == EINVAL
 
 
 def test_fbp_batch_validation(lib):

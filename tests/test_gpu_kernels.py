@@ -164,6 +164,131 @@ def test_backproject_is_deterministic(xct):
         assert torch.equal(a, b)
 
 
+# ---------------------------------------------------------------- front end
+FE_CASES = [
+    # (N_p, N_r, N_c, row_begin, slices, sigma, counts dtype, filtered dtype, window)
+    (37, 5, 97, 1, 3, 0.0, torch.uint16, torch.float32, "ram_lak"),
+    (37, 5, 97, 0, 5, 1.3, torch.float32, torch.float32, "hann"),
+    (20, 3, 250, 2, 1, 4.0, torch.uint16, torch.float32, "shepp_logan"),
+    (21, 4, 300, 1, 3, 2.2, torch.uint16, torch.float16, "hann"),   # 63 rows: a lone last row
+    (6, 2, 8192, 0, 2, 1.0, torch.uint16, torch.float32, "hann"),   # widest detector
+    (9, 2, 1, 0, 2, 0.5, torch.float32, torch.float32, "ram_lak"),  # one channel
+    (11, 3, 40, 0, 3, 15.0, torch.uint16, torch.float32, "ram_lak"),  # blur wider than the row
+]
+
+
+@pytest.mark.parametrize("case", range(len(FE_CASES)))
+def test_preprocess_filter_matches_oracle(xct, case):
+    from oracle import pipeline as pl
+
+    n_p, n_r, n_c, r0, S, sigma, cdt, fdt, window = FE_CASES[case]
+    rng = np.random.default_rng(400 + case)
+    g = _geom(n_angles=n_p, n_det=n_c, nx=8, ny=8, det_pitch=0.9)
+    dark, flat = synth.detector_fields(n_r, n_c, 400 + case)
+    lines = torch.as_tensor(rng.uniform(0.0, 3.0, (n_r, n_p, n_c)))
+    proj = synth.raw_counts(lines, dark, flat, 1.0, dtype=cdt)
+    if cdt == torch.uint16:
+        # dead and saturated pixels: counts below the dark current, a flat
+        # field below it, both clamped at the floor
+        pn = proj.numpy()
+        pn[0, r0, 0] = 20
+        pn[n_p - 1, n_r - 1, n_c - 1] = 0
+        flat[r0, n_c // 2] = dark[r0, n_c // 2] - 5.0
+    out = torch.empty((S, n_p, n_c), dtype=fdt, device="cuda")
+    say("front end", case)
+    proj_dev = proj.view(torch.int16).cuda().view(torch.uint16) if cdt == torch.uint16 else proj.cuda()
+    xct.xct_preprocess_filter(g, proj_dev, dark.cuda(), flat.cuda(), r0, out, window, 1.0, sigma)
+    torch.cuda.synchronize()
+    counts = proj.numpy().astype(np.float64)
+    p = pl.preprocess(counts, dark.numpy(), flat.numpy(), r0, S, 1.0, sigma)
+    ref = oracle.filter(p, g.det_pitch, window)
+    got = out.to(torch.float32).cpu().numpy()
+    err = rel_l2(got, ref)
+    tol = 2e-5 if fdt == torch.float32 else 2e-3
+    assert err < tol, err
+
+
+def test_preprocess_filter_without_blur_equals_filter_of_line_integrals(xct):
+    """sigma = 0 and FP32 line integrals given as counts of a unit flat field and
+    zero dark current (I = exp(-p)): the front end reduces to xct_filter of p,
+    up to the FP32 logarithm."""
+    rng = np.random.default_rng(17)
+    n_p, n_r, n_c = 30, 4, 120
+    g = _geom(n_angles=n_p, n_det=n_c, nx=8, ny=8)
+    p = rng.uniform(0.0, 2.0, (n_r, n_p, n_c))
+    proj = torch.as_tensor(np.exp(-p).transpose(1, 0, 2).copy(), dtype=torch.float32).cuda()
+    dark = torch.zeros((n_r, n_c), device="cuda")
+    flat = torch.ones((n_r, n_c), device="cuda")
+    a = torch.empty((n_r, n_p, n_c), device="cuda")
+    xct.xct_preprocess_filter(g, proj, dark, flat, 0, a, "shepp_logan", 1e-30, 0.0)
+    b = torch.empty_like(a)
+    xct.xct_filter(g, to_dev(p), b, "shepp_logan")
+    torch.cuda.synchronize()
+    assert rel_l2(a.cpu().numpy(), b.cpu().numpy().astype(np.float64)) < 1e-5
+
+
+# ---------------------------------------------------------------- CT-number codes
+def _hu_params(a, b, d=4000.0):
+    """(mu_water, hu_min, hu_max) whose code map is code = a mu + b."""
+    span = 65535.0 / d
+    mu_w = 1000.0 * span / a
+    hu_min = -1000.0 - b / span
+    return mu_w, hu_min, hu_min + d
+
+
+@pytest.mark.parametrize("case", [0, 5, 11])   # generic path, symmetric 96- and 192-entry windows
+@pytest.mark.parametrize("clip", ["low", "high"])
+def test_backproject_u16_matches_oracle_codes(xct, case, clip):
+    from oracle import pipeline as pl
+
+    rng = np.random.default_rng(300 + case)
+    g = _case_geom(BP_CASES[case], rng)
+    S = 3
+    q32 = rng.standard_normal((S, g.n_angles, g.n_det)).astype(np.float32)
+    ref = oracle.backproject(q32.astype(np.float64), g, 0.37)
+    sigma = float(ref.std())
+    # about 300 codes per standard deviation; a third of the voxels clip at
+    # one end of the code range
+    a = 300.0 / sigma
+    b = 150.0 if clip == "low" else 65535.0 - 150.0
+    mu_w, lo, hi = _hu_params(a, b)
+    out = torch.empty((S, g.ny, g.nx), dtype=torch.uint16, device="cuda")
+    say("u16", case, clip)
+    xct.xct_backproject_u16(g, to_dev(q32), out, 0.37, mu_w, lo, hi)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.int64)
+    want = pl.hu_codes_fp32(ref, mu_w, lo, hi).astype(np.int64)
+    # the FP32 image is within 2e-5 max|mu| of the FP64 one; codes whose FP64
+    # value lies farther than that from a rounding boundary are decided alike
+    margin = pl.hu_affine(mu_w, lo, hi)[0] * 2e-5 * float(np.abs(ref).max()) + 1e-3
+    far = pl.hu_rounding_distance(ref, mu_w, lo, hi) > margin
+    assert far.mean() > 0.9
+    np.testing.assert_array_equal(got[far], want[far])
+    assert np.abs(got - want).max() <= 1
+    edge = 0 if clip == "low" else 65535
+    assert np.mean(want == edge) > 0.1 and np.array_equal(got[want == edge], want[want == edge])
+
+
+def test_backproject_u16_is_the_fp32_image_quantised(xct):
+    """The CT-number epilogue applied to the FP32 back-projection, bit for bit:
+    fl(fl(v a) + b), rounded half to even, clamped (the documented map)."""
+    rng = np.random.default_rng(13)
+    g = _geom(n_angles=90, n_det=181, nx=128, ny=128)
+    q = to_dev(rng.standard_normal((2, 90, 181)))
+    img = torch.empty((2, 128, 128), device="cuda")
+    codes = torch.empty((2, 128, 128), dtype=torch.uint16, device="cuda")
+    mu_w, lo, hi = 0.05, -1500.0, 2500.0
+    xct.xct_backproject(g, q, img, 0.1, False)
+    xct.xct_backproject_u16(g, q, codes, 0.1, mu_w, lo, hi)
+    torch.cuda.synchronize()
+    span = 65535.0 / (hi - lo)
+    a32, b32 = np.float32(1000.0 / mu_w * span), np.float32((-1000.0 - lo) * span)
+    v = img.cpu().numpy()
+    t = (v * a32).astype(np.float32) + b32
+    want = np.clip(np.rint(t.astype(np.float32)), 0, 65535).astype(np.uint16)
+    np.testing.assert_array_equal(codes.cpu().numpy(), want)
+
+
 def test_forward_accumulate_and_scale(xct):
     """sino = sino0 - 0.7 A x in one pass (the residual form)."""
     rng = np.random.default_rng(14)
