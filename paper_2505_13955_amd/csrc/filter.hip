@@ -59,6 +59,12 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b)
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// LDS position of transform element i: bits 0-3 XORed with bits 3-6.  A
+// permutation within aligned groups of 128 elements that takes the four-way
+// bank conflicts of the span-1 and span-4 passes' strided writes down to at
+// most two-way, with no extra LDS.
+__device__ __forceinline__ int sw(int i) { return i ^ ((i >> 3) & 15); }
+
 // One radix-2 Stockham pass of span Ns (only as the first pass, Ns = 1).
 __device__ __forceinline__ void pass_r2(float2 *z, int L, int Ns, const float2 *tw, int tid, int nt)
 {
@@ -68,8 +74,8 @@ __device__ __forceinline__ void pass_r2(float2 *z, int L, int Ns, const float2 *
     for (int q = 0; q < 8; ++q) {
         const int j = tid + q * nt;
         if (j < half) {
-            v0[q] = z[j];
-            v1[q] = z[j + half];
+            v0[q] = z[sw(j)];
+            v1[q] = z[sw(j + half)];
         }
     }
     __syncthreads();
@@ -80,24 +86,35 @@ __device__ __forceinline__ void pass_r2(float2 *z, int L, int Ns, const float2 *
             const int k = j & (Ns - 1);
             const float2 b = (Ns > 1) ? cmul(v1[q], tw[k * (L / (2 * Ns))]) : v1[q];
             const int base = ((j - k) << 1) + k;
-            z[base] = make_float2(v0[q].x + b.x, v0[q].y + b.y);
-            z[base + Ns] = make_float2(v0[q].x - b.x, v0[q].y - b.y);
+            z[sw(base)] = make_float2(v0[q].x + b.x, v0[q].y + b.y);
+            z[sw(base + Ns)] = make_float2(v0[q].x - b.x, v0[q].y - b.y);
         }
     }
     __syncthreads();
 }
 
-// One radix-4 Stockham pass of span Ns.
+// One radix-4 Stockham pass of span Ns.  The twiddles are fetched before the
+// LDS reads and the barrier, so their latency overlaps both.
 __device__ __forceinline__ void pass_r4(float2 *z, int L, int Ns, const float2 *tw, int tid, int nt)
 {
-    float2 v[4][4];
+    float2 v[4][4], w[4][3];
     const int quarter = L >> 2;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = tid + q * nt;
+        if (Ns > 1 && j < quarter) {
+            const int e1 = (j & (Ns - 1)) * (quarter / Ns);
+            w[q][0] = tw[e1];
+            w[q][1] = tw[2 * e1];
+            w[q][2] = tw[3 * e1];
+        }
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int j = tid + q * nt;
         if (j < quarter) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) v[q][r] = z[j + r * quarter];
+            for (int r = 0; r < 4; ++r) v[q][r] = z[sw(j + r * quarter)];
         }
     }
     __syncthreads();
@@ -108,20 +125,19 @@ __device__ __forceinline__ void pass_r4(float2 *z, int L, int Ns, const float2 *
             const int k = j & (Ns - 1);
             float2 x0 = v[q][0], x1 = v[q][1], x2 = v[q][2], x3 = v[q][3];
             if (Ns > 1) {
-                const int e1 = k * (quarter / Ns);
-                x1 = cmul(x1, tw[e1]);
-                x2 = cmul(x2, tw[2 * e1]);
-                x3 = cmul(x3, tw[3 * e1]);
+                x1 = cmul(x1, w[q][0]);
+                x2 = cmul(x2, w[q][1]);
+                x3 = cmul(x3, w[q][2]);
             }
             const float2 a0 = make_float2(x0.x + x2.x, x0.y + x2.y);
             const float2 a1 = make_float2(x0.x - x2.x, x0.y - x2.y);
             const float2 a2 = make_float2(x1.x + x3.x, x1.y + x3.y);
             const float2 a3 = make_float2(x1.y - x3.y, x3.x - x1.x);  // -i (x1 - x3)
             const int base = ((j - k) << 2) + k;
-            z[base] = make_float2(a0.x + a2.x, a0.y + a2.y);
-            z[base + Ns] = make_float2(a1.x + a3.x, a1.y + a3.y);
-            z[base + 2 * Ns] = make_float2(a0.x - a2.x, a0.y - a2.y);
-            z[base + 3 * Ns] = make_float2(a1.x - a3.x, a1.y - a3.y);
+            z[sw(base)] = make_float2(a0.x + a2.x, a0.y + a2.y);
+            z[sw(base + Ns)] = make_float2(a1.x + a3.x, a1.y + a3.y);
+            z[sw(base + 2 * Ns)] = make_float2(a0.x - a2.x, a0.y - a2.y);
+            z[sw(base + 3 * Ns)] = make_float2(a1.x - a3.x, a1.y - a3.y);
         }
     }
     __syncthreads();
@@ -168,11 +184,11 @@ __device__ __forceinline__ void load_front_end(float2 *z, const FilterArgs &a, i
         drow[h] = pre.dark + det_row * nc;
         frow[h] = pre.flat + det_row * nc;
     }
-    float2 *stage = pre.radius > 0 ? z + (L >> 1) : z;
+    const int stage = pre.radius > 0 ? (L >> 1) : 0;  // first element of the staged rows
     for (int n = tid; n < nc; n += nt) {
         const float p0 = beer_lambert(ld_in(src[0], n), drow[0][n], frow[0][n], pre.floor);
         const float p1 = has1 ? beer_lambert(ld_in(src[1], n), drow[1][n], frow[1][n], pre.floor) : 0.0f;
-        stage[n] = make_float2(p0, p1);
+        z[sw(stage + n)] = make_float2(p0, p1);
     }
     if (pre.radius > 0) {
         __syncthreads();
@@ -181,15 +197,15 @@ __device__ __forceinline__ void load_front_end(float2 *z, const FilterArgs &a, i
             float b0 = 0.0f, b1 = 0.0f;
             for (int m = -R; m <= R; ++m) {
                 const float g = pre.taps[m + R];
-                const float2 v = stage[min(max(n + m, 0), nc - 1)];
+                const float2 v = z[sw(stage + min(max(n + m, 0), nc - 1))];
                 b0 = fmaf(g, v.x, b0);
                 b1 = fmaf(g, v.y, b1);
             }
-            z[n] = make_float2(b0, b1);
+            z[sw(n)] = make_float2(b0, b1);
         }
         __syncthreads();
     }
-    for (int n = nc + tid; n < L; n += nt) z[n] = make_float2(0.0f, 0.0f);
+    for (int n = nc + tid; n < L; n += nt) z[sw(n)] = make_float2(0.0f, 0.0f);
 }
 
 template <typename TI, typename TO, bool PRE>
@@ -206,21 +222,26 @@ __global__ __launch_bounds__(1024) void filter_kernel(FilterArgs a)
     } else {
         const TI *p0 = static_cast<const TI *>(a.in) + r0 * nc;
         const TI *p1 = p0 + nc;
-        for (int n = tid; n < L; n += nt) {
-            float x0 = 0.0f, x1 = 0.0f;
-            if (n < nc) {
-                x0 = ld_in(p0, n);
-                if (has1) x1 = ld_in(p1, n);
+        // four elements of each row in flight per thread
+        for (int n0 = tid; n0 < L; n0 += 4 * nt) {
+            float x0[4], x1[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int n = n0 + u * nt;
+                x0[u] = n < nc ? ld_in(p0, n) : 0.0f;
+                x1[u] = (n < nc && has1) ? ld_in(p1, n) : 0.0f;
             }
-            z[n] = make_float2(x0, x1);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (n0 + u * nt < L) z[sw(n0 + u * nt)] = make_float2(x0[u], x1[u]);
         }
     }
     __syncthreads();
     fft_forward(z, L, a.log2L, a.tw, tid, nt);
     for (int n = tid; n < L; n += nt) {
         const float h = a.H[n];
-        const float2 v = z[n];
-        z[n] = make_float2(v.x * h, -v.y * h);
+        const float2 v = z[sw(n)];
+        z[sw(n)] = make_float2(v.x * h, -v.y * h);
     }
     __syncthreads();
     fft_forward(z, L, a.log2L, a.tw, tid, nt);
@@ -228,7 +249,7 @@ __global__ __launch_bounds__(1024) void filter_kernel(FilterArgs a)
     TO *o0 = static_cast<TO *>(a.out) + r0 * nc;
     TO *o1 = o0 + nc;
     for (int n = tid; n < nc; n += nt) {
-        const float2 v = z[n];
+        const float2 v = z[sw(n)];
         st_out(o0, n, v.x);
         if (has1) st_out(o1, n, -v.y);
     }
