@@ -187,6 +187,50 @@ def fbp(p, geom, window: str) -> np.ndarray:
     return backproject(filter(p, geom.det_pitch, window), geom, fbp_weight(geom))
 
 
+def offset_weights(n_det: int, center: float, overlap: float) -> np.ndarray:
+    """Redundancy weights w[n] of a full-turn scan whose rotation axis sits at
+    bin ``center`` (offset scan, Section V-A b): a ray measured at angle th and
+    bin n is measured again at th + pi and bin 2c - n, and the two weights sum
+    to one.  Reading (the paper gives no weighting): with t = (n - c)/overlap,
+    signed so that t > 0 on the longer side of the detector,
+    w = 0 for t <= -1, sin^2(pi (1 + t) / 4) for |t| < 1, 1 for t >= 1."""
+    n = np.arange(n_det, dtype=np.float64)
+    side = 1.0 if (n_det - 1 - center) >= center else -1.0
+    t = side * (n - center) / overlap
+    return np.where(t <= -1.0, 0.0, np.where(t >= 1.0, 1.0, np.sin(0.25 * math.pi * (1.0 + t)) ** 2))
+
+
+def offset_virtual_detector(n_det: int, center: float) -> tuple[int, float, int]:
+    """(N_v, c_v, first): the detector of a full-turn scan mirrored about the
+    axis, bins 2c - (N_c - 1) .. N_c - 1 when the longer side is to the right
+    (else 0 .. 2c), renumbered from 0; `first` is the virtual bin of physical
+    bin 0.  Needs 2c integral."""
+    two_c = int(round(2.0 * center))
+    if (n_det - 1 - center) >= center:
+        lo = two_c - (n_det - 1)
+        return n_det - lo, center - lo, -lo
+    return two_c + 1, center, 0
+
+
+def offset_rows(p, n_det: int, center: float, overlap: float) -> np.ndarray:
+    """Rows of an offset scan weighted by offset_weights and placed on the
+    virtual detector (zero on the bins the physical detector does not see)."""
+    p = _f64(p)
+    nv, _, first = offset_virtual_detector(n_det, center)
+    out = np.zeros(p.shape[:-1] + (nv,))
+    out[..., first:first + n_det] = p * offset_weights(n_det, center, overlap)
+    return out
+
+
+def fbp_offset(p, geom, window: str, overlap: float) -> np.ndarray:
+    """FBP of a full-turn offset scan: weighted rows on the virtual detector,
+    filtered there, back-projected over the full turn with weight 2 pi / N_p
+    through the virtual detector geometry."""
+    nv, cv, _ = offset_virtual_detector(geom.n_det, geom.center)
+    q = filter(offset_rows(p, geom.n_det, geom.center, overlap), geom.det_pitch, window)
+    return backproject(q, geom.replace(n_det=nv, center=cv), 2.0 * math.pi / geom.n_angles)
+
+
 def fbp_pixels(p, geom, window: str, pixels) -> np.ndarray:
     """FBP at the listed (slice, row, col) pixels; the filter runs on every row."""
     return backproject_pixels(filter(p, geom.det_pitch, window), geom, pixels, fbp_weight(geom))
