@@ -117,6 +117,32 @@ def measure_raw_pipeline(xct, torch, synth, spec, p64, filt, stream, steps, warm
     }
 
 
+def measure_offset_scan(xct, torch, configs, stream, steps, warmup):
+    """Full-turn offset scan through xct_fbp_batch: 8 x 4096^2, 8192 angles,
+    4096 bins with the axis at bin 1024, redundancy overlap 1024, Hann
+    (weighted rows filtered on the 6143-bin virtual detector, one symmetric
+    back-projection launch over both half turns)."""
+    spec = configs.c6()
+    g = spec.geom
+    S = spec.n_slices
+    p = torch.empty((S, g.n_angles, g.n_det), dtype=torch.float32, device="cuda")
+    for s in range(S):
+        p[s] = spec.sinogram(s, device="cuda").to(torch.float32)
+    img = torch.empty((S, g.ny, g.nx), dtype=torch.float32, device="cuda")
+    slabs = [(g, p, img, spec.offset_overlap)]
+    ws = torch.empty(xct.xct_fbp_workspace_bytes(slabs), dtype=torch.uint8, device="cuda")
+    ms = _timed(torch, stream, lambda: xct.xct_fbp_batch(slabs, spec.window, workspace=ws),
+                steps, warmup)
+    log(f"offset scan: {ms:.3f} ms")
+    del p, img, ws
+    return {
+        "workload": (
+            "8 x 4096^2 offset scan, 8192 angles over a full turn, 4096 bins, axis at bin 1024, "
+            "overlap 1024, Hann; xct_fbp_batch"),
+        "ms": ms, "gups": spec.updates / (ms * 1e-3) / 1e9, "updates": spec.updates,
+    }
+
+
 def measure_uneven_batch(xct, torch, configs, encode_storage, stream, steps, warmup):
     """Filter + back-projection of the uneven batch (24 x 512^2, 12 x 1024^2,
     4 x 2048^2, BF16-stored, Ram-Lak) in one persistent launch per kernel,
@@ -317,6 +343,9 @@ def main():
     if not args.main_only:
         extra["uneven_batch"] = measure_uneven_batch(xct, torch, configs, encode_storage, stream,
                                                      args.steps, args.warmup)
+        torch.cuda.empty_cache()
+        extra["offset_scan"] = measure_offset_scan(xct, torch, configs, stream, args.steps,
+                                                   args.warmup)
         torch.cuda.empty_cache()
         extra["adjoint_pair"] = measure_adjoint_pair(xct, torch, configs, stream, args.steps,
                                                      args.warmup)

@@ -97,6 +97,34 @@ typedef struct {
 int xct_filter(const xct_geometry *g, int32_t n_slices, const void *sino, int32_t sino_t,
                void *filtered, int32_t filtered_t, int32_t window, xct_stream stream);
 
+/* Offset scans (Section V-A b): the sample is shifted laterally so that the
+ * rotation axis sits off the detector centre, and a full turn is acquired;
+ * every ray near the axis is measured twice (bin n at angle th, bin 2c - n at
+ * th + pi) and the rest once.  Reconstruction weights each row by the
+ * redundancy weight
+ *   w[n] = 0 (t <= -1),  sin^2(pi (1 + t) / 4) (|t| < 1),  1 (t >= 1),
+ *   t = (n - c) / overlap, signed positive on the detector's longer side
+ * (w[n] + w[2c - n] = 1), places it on the virtual detector (the physical bins
+ * and their mirror images about the axis), ramp-filters it there, and
+ * back-projects the full turn through the virtual detector with weight
+ * 2 pi / N_p.  For parallel beams this equals half-turn FBP on the virtual
+ * detector.  Requires 2c integral, 0 <= c <= N_c - 1 and
+ * 0 < overlap <= min(c, N_c - 1 - c).
+ *
+ * xct_offset_detector: size and axis of the virtual detector,
+ *   n_virtual = 2 (N_c - 1 - c) + 1 and center_virtual = N_c - 1 - c when the
+ *   longer side is right of the axis, else 2c + 1 and c.
+ * xct_filter_offset: filtered [n_slices][N_p][n_virtual] of filtered_t from
+ *   sino [n_slices][N_p][N_c]; n_virtual <= 8192 (else XCT_ETOOBIG); not in
+ *   place.  Back-project it with the geometry's n_det = n_virtual, center =
+ *   center_virtual and scale = 2 pi / N_p; angle sets of a full turn closed
+ *   under quarter turns (N_p divisible by 4, uniform) take the symmetric
+ *   kernel. */
+int xct_offset_detector(const xct_geometry *g, int32_t *n_virtual, double *center_virtual);
+int xct_filter_offset(const xct_geometry *g, int32_t n_slices, const void *sino, int32_t sino_t,
+                      void *filtered, int32_t filtered_t, int32_t window, double overlap,
+                      xct_stream stream);
+
 /* Pre-processing front end fused into the filter (Section V-A c, stage 2:
  * Beer-Lambert conversion, Gaussian blur, then filtering), which also regroups
  * the projection stack as acquired into one sinogram per detector row:
@@ -164,6 +192,11 @@ typedef struct {
     int32_t n_slices;
     const void *sino; /* device [n_slices][N_p][N_c] of the batch's sino_t  */
     float *image;     /* device [n_slices][N_y][N_x] FP32, overwritten      */
+    double offset_overlap; /* 0: a half-turn scan (FBP weight pi / N_p);
+                              > 0: a full-turn offset scan reconstructed as
+                              xct_filter_offset with this overlap, then the
+                              back-projection through the virtual detector
+                              with weight 2 pi / N_p                        */
 } xct_slab;
 
 /* Bytes of device workspace xct_fbp_batch needs for these slabs when the

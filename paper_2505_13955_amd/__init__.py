@@ -18,6 +18,7 @@ from .xct import (  # noqa: F401
     adjoint_scale,
     backproject,
     fbp,
+    fbp_offset,
     fbp_weight,
     filter,
     forward_project,
@@ -30,7 +31,9 @@ from .xct import (  # noqa: F401
     xct_fbp_batch,
     xct_fbp_workspace_bytes,
     xct_filter,
+    xct_filter_offset,
     xct_forward_project,
+    xct_offset_detector,
     xct_preprocess_filter,
     xct_sqdist_f64,
     xct_version,

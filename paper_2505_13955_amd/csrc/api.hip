@@ -82,6 +82,7 @@ std::unordered_map<std::string, GeoTables> g_geo;
 std::unordered_map<std::string, FilterTables> g_filt;
 std::unordered_map<std::string, FPTables> g_fp;
 std::unordered_map<std::string, float *> g_blur;
+std::unordered_map<std::string, float *> g_offset;
 
 template <typename T>
 void key_append(std::string &k, const T &v)
@@ -168,6 +169,82 @@ int blur_taps(float sigma, int radius, const float **out)
     }
     g_blur.emplace(key, d);
     *out = d;
+    return XCT_OK;
+}
+
+// Virtual detector of a full-turn scan: the physical bins and their mirror
+// images about the axis (bin 2c - n), renumbered from 0.  `first` is the
+// virtual bin of physical bin 0.  Needs 2c integral and the axis on the
+// detector.
+void offset_virtual(const xct_geometry *g, int *nv, double *cv, int *first)
+{
+    const int nc = g->n_det;
+    const int two_c = (int)std::nearbyint(2.0 * g->center);
+    if ((nc - 1) - g->center >= g->center) {  // longer side to the right of the axis
+        const int lo = two_c - (nc - 1);
+        *nv = nc - lo;
+        *cv = g->center - lo;
+        *first = -lo;
+    } else {
+        *nv = two_c + 1;
+        *cv = g->center;
+        *first = 0;
+    }
+}
+
+// Redundancy weights of a full-turn scan (offset scan, Section V-A b): with
+// t = (n - c) / overlap, positive on the detector's longer side,
+// w = 0 (t <= -1), sin^2(pi (1 + t) / 4) (|t| < 1), 1 (t >= 1), so that the
+// two measurements of every ray, bins n and 2c - n half a turn apart, weigh
+// one together.  FP64 on the host, rounded once, cached on the device.
+int offset_weights(const xct_geometry *g, double overlap, const float **out)
+{
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    std::string key;
+    key_append(key, dev);
+    key_append(key, g->n_det);
+    key_append(key, g->center);
+    key_append(key, overlap);
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_offset.find(key);
+    if (it != g_offset.end()) {
+        *out = it->second;
+        return XCT_OK;
+    }
+    const int nc = g->n_det;
+    const double side = ((nc - 1) - g->center >= g->center) ? 1.0 : -1.0;
+    std::vector<float> w(nc);
+    for (int n = 0; n < nc; ++n) {
+        const double t = side * ((double)n - g->center) / overlap;
+        double v = 1.0;
+        if (t <= -1.0) v = 0.0;
+        else if (t < 1.0) {
+            const double sn = std::sin(0.25 * M_PI * (1.0 + t));
+            v = sn * sn;
+        }
+        w[n] = (float)v;
+    }
+    float *d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(float) * nc);
+    if (e == hipSuccess) e = hipMemcpy(d, w.data(), sizeof(float) * nc, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (d) (void)hipFree(d);
+        return hip_fail(e);
+    }
+    g_offset.emplace(key, d);
+    *out = d;
+    return XCT_OK;
+}
+
+// Checks shared by the offset-scan entry points.
+int check_offset(const xct_geometry *g, double overlap)
+{
+    const double m = 2.0 * g->center;
+    if (std::fabs(m - std::nearbyint(m)) > 1e-9) return XCT_EINVAL;
+    if (g->center < 0.0 || g->center > g->n_det - 1) return XCT_EINVAL;
+    const double short_side = std::min(g->center, (g->n_det - 1) - g->center);
+    if (!std::isfinite(overlap) || !(overlap > 0.0) || overlap > short_side + 1e-9) return XCT_EINVAL;
     return XCT_OK;
 }
 
@@ -331,19 +408,31 @@ int device_cus()
 // floor, the right tap and the one-bin margin of the anchor.
 int window_entries(double ratio) { return (int)std::ceil((kTile - 1) * std::sqrt(2.0) * ratio + 1e-3) + 3; }
 
-bool symmetric_ok(const xct_geometry *g)
+// Half-turn sets of a symmetric angle set: 1 when angle k + N_p/2 is angle k
+// plus a quarter turn for every k < N_p/2 (a half turn); 2 when each half of
+// the angles is such a set (a full turn, as in offset scans); 0 otherwise,
+// or when the slice is not square and even, 2c is not integral, or the
+// windows do not fit the symmetric kernel.
+int symmetric_sets(const xct_geometry *g)
 {
-    if (g->nx != g->ny || (g->nx & 1) || (g->n_angles & 1)) return false;
-    if (!bp_sym_window(window_entries(g->pixel_size / g->det_pitch))) return false;
+    if (g->nx != g->ny || (g->nx & 1) || (g->n_angles & 1)) return 0;
+    if (!bp_sym_window(window_entries(g->pixel_size / g->det_pitch))) return 0;
     const double m = 2.0 * g->center;
-    if (std::fabs(m - std::nearbyint(m)) > 1e-9) return false;
-    const int H = g->n_angles / 2;
-    for (int k = 0; k < H; ++k)
-        if (std::fabs(g->angles[k + H] - g->angles[k] - 0.5 * M_PI) > 1e-9) return false;
-    return true;
+    if (std::fabs(m - std::nearbyint(m)) > 1e-9) return 0;
+    auto quarter_closed = [g](int k_begin, int n) {
+        const int H = n / 2;
+        for (int k = 0; k < H; ++k)
+            if (std::fabs(g->angles[k_begin + k + H] - g->angles[k_begin + k] - 0.5 * M_PI) > 1e-9)
+                return false;
+        return true;
+    };
+    const int np = g->n_angles;
+    if (quarter_closed(0, np)) return 1;
+    if (np % 4 == 0 && quarter_closed(0, np / 2) && quarter_closed(np / 2, np / 2)) return 2;
+    return 0;
 }
 
-int choose_path(const xct_geometry *g) { return symmetric_ok(g) ? kPathSymmetric : kPathGeneric; }
+int choose_path(const xct_geometry *g) { return symmetric_sets(g) ? kPathSymmetric : kPathGeneric; }
 
 struct BPJob {
     const xct_geometry *g;
@@ -421,6 +510,7 @@ int launch_bp_jobs(std::vector<BPJob> jobs, int dtype, unsigned int *counter, hi
         sl.tiles_x = tx;
         sl.tiles_y = ty;
         sl.mirror = path != kPathGeneric ? (int32_t)std::nearbyint(2.0 * j.g->center) : 0;
+        sl.sets = path != kPathGeneric ? symmetric_sets(j.g) : 1;
         sl.scale = j.scale;
         sl.accumulate = j.accumulate;
         sl.out_u16 = j.out_u16;
@@ -499,6 +589,8 @@ void xct_cache_clear(void)
         (void)hipFree(kv.second.blocks);
     }
     for (auto &kv : g_blur) (void)hipFree(kv.second);
+    for (auto &kv : g_offset) (void)hipFree(kv.second);
+    g_offset.clear();
     g_geo.clear();
     g_filt.clear();
     g_fp.clear();
@@ -525,6 +617,57 @@ int xct_filter(const xct_geometry *g, int32_t n_slices, const void *sino, int32_
     a.H = ft.H;
     a.rows = (int64_t)n_slices * g->n_angles;
     a.nc = g->n_det;
+    a.in_len = g->n_det;
+    a.L = L;
+    a.log2L = lg;
+    hipError_t e = launch_filter(a, sino_t, filtered_t, (hipStream_t)stream);
+    return e == hipSuccess ? XCT_OK : hip_fail(e);
+}
+
+int xct_offset_detector(const xct_geometry *g, int32_t *n_virtual, double *center_virtual)
+{
+    if (int rc = check_geometry(g, false)) return rc;
+    if (!n_virtual || !center_virtual) return XCT_EINVAL;
+    const double m = 2.0 * g->center;
+    if (std::fabs(m - std::nearbyint(m)) > 1e-9) return XCT_EINVAL;
+    if (g->center < 0.0 || g->center > g->n_det - 1) return XCT_EINVAL;
+    int nv, first;
+    double cv;
+    offset_virtual(g, &nv, &cv, &first);
+    *n_virtual = nv;
+    *center_virtual = cv;
+    return XCT_OK;
+}
+
+int xct_filter_offset(const xct_geometry *g, int32_t n_slices, const void *sino, int32_t sino_t,
+                      void *filtered, int32_t filtered_t, int32_t window, double overlap,
+                      xct_stream stream)
+{
+    if (int rc = check_geometry(g, false)) return rc;
+    if (int rc = check_slices(g, n_slices)) return rc;
+    if (!sino || !filtered || sino == filtered) return XCT_EINVAL;
+    if (!dtype_ok(sino_t) || !dtype_ok(filtered_t)) return XCT_EDTYPE;
+    if (window < XCT_RAM_LAK || window > XCT_HANN) return XCT_EDTYPE;
+    if (int rc = check_offset(g, overlap)) return rc;
+    int nv, first;
+    double cv;
+    offset_virtual(g, &nv, &cv, &first);
+    if (nv > kMaxFFT / 2) return XCT_ETOOBIG;
+    FilterTables ft;
+    int L, lg;
+    if (int rc = filter_tables(nv, window, g->det_pitch, &ft, &L, &lg)) return rc;
+    const float *w = nullptr;
+    if (int rc = offset_weights(g, overlap, &w)) return rc;
+    FilterArgs a{};
+    a.in = sino;
+    a.out = filtered;
+    a.tw = ft.tw;
+    a.H = ft.H;
+    a.weight = w;
+    a.in_first = first;
+    a.in_len = g->n_det;
+    a.rows = (int64_t)n_slices * g->n_angles;
+    a.nc = nv;
     a.L = L;
     a.log2L = lg;
     hipError_t e = launch_filter(a, sino_t, filtered_t, (hipStream_t)stream);
@@ -664,6 +807,17 @@ int xct_forward_project(const xct_geometry *g, int32_t n_slices, const float *im
     return e == hipSuccess ? XCT_OK : hip_fail(e);
 }
 
+// Detector bins of a slab's filtered rows: the virtual (mirrored) detector
+// for an offset scan, the physical one otherwise.
+static int filtered_bins(const xct_slab &sl)
+{
+    if (sl.offset_overlap == 0.0) return sl.geom.n_det;
+    int nv, first;
+    double cv;
+    offset_virtual(&sl.geom, &nv, &cv, &first);
+    return nv;
+}
+
 static int check_slabs(const xct_slab *slabs, int32_t n_slabs, bool need_data)
 {
     if (!slabs || n_slabs <= 0) return XCT_EINVAL;
@@ -671,7 +825,9 @@ static int check_slabs(const xct_slab *slabs, int32_t n_slabs, bool need_data)
     for (int i = 0; i < n_slabs; ++i) {
         if (int rc = check_geometry(&slabs[i].geom, true)) return rc;
         if (int rc = check_slices(&slabs[i].geom, slabs[i].n_slices)) return rc;
-        if (slabs[i].geom.n_det > kMaxFFT / 2) return XCT_ETOOBIG;
+        if (slabs[i].offset_overlap != 0.0)
+            if (int rc = check_offset(&slabs[i].geom, slabs[i].offset_overlap)) return rc;
+        if (filtered_bins(slabs[i]) > kMaxFFT / 2) return XCT_ETOOBIG;
         if (need_data && (!slabs[i].sino || !slabs[i].image)) return XCT_EINVAL;
     }
     return XCT_OK;
@@ -683,7 +839,8 @@ size_t xct_fbp_workspace_bytes(const xct_slab *slabs, int32_t n_slabs, int32_t f
     size_t bytes = 256;  // work counters
     for (int i = 0; i < n_slabs; ++i) {
         const xct_geometry &g = slabs[i].geom;
-        bytes += align256((size_t)slabs[i].n_slices * g.n_angles * g.n_det * dtype_size(filtered_t));
+        bytes += align256((size_t)slabs[i].n_slices * g.n_angles * filtered_bins(slabs[i]) *
+                          dtype_size(filtered_t));
     }
     return bytes;
 }
@@ -702,19 +859,35 @@ int xct_fbp_batch(const xct_slab *slabs, int32_t n_slabs, int32_t sino_t, int32_
     unsigned int *counters = reinterpret_cast<unsigned int *>(ws);
     size_t off = 256;
     std::vector<BPJob> jobs_by_path[2];
+    // back-projection geometry of offset slabs (virtual detector); lives until
+    // the launches below have read it
+    std::vector<xct_geometry> virt(n_slabs);
     for (int i = 0; i < n_slabs; ++i) {
         const xct_slab &sl = slabs[i];
         const xct_geometry *g = &sl.geom;
         void *filt = ws + off;
-        off += align256((size_t)sl.n_slices * g->n_angles * g->n_det * dtype_size(filtered_t));
-        if (int rc = xct_filter(g, sl.n_slices, sl.sino, sino_t, filt, filtered_t, window, stream))
+        off += align256((size_t)sl.n_slices * g->n_angles * filtered_bins(sl) * dtype_size(filtered_t));
+        double weight = M_PI / g->n_angles;
+        if (sl.offset_overlap != 0.0) {
+            // full-turn offset scan: redundancy-weighted rows filtered on the
+            // virtual detector, back-projected with weight 2 pi / N_p
+            if (int rc = xct_filter_offset(g, sl.n_slices, sl.sino, sino_t, filt, filtered_t, window,
+                                           sl.offset_overlap, stream))
+                return rc;
+            int first;
+            virt[i] = *g;
+            offset_virtual(g, &virt[i].n_det, &virt[i].center, &first);
+            g = &virt[i];
+            weight = 2.0 * M_PI / g->n_angles;
+        } else if (int rc = xct_filter(g, sl.n_slices, sl.sino, sino_t, filt, filtered_t, window, stream)) {
             return rc;
+        }
         BPJob j;
         j.g = g;
         j.n_slices = sl.n_slices;
         j.sino = filt;
         j.image = sl.image;
-        j.scale = (float)(M_PI / g->n_angles);
+        j.scale = (float)weight;
         j.accumulate = 0;
         j.path = choose_path(g);
         if (int rc = geo_tables(g, &j.t)) return rc;

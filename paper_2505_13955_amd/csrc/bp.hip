@@ -90,6 +90,7 @@ __device__ __forceinline__ void select_slab(KBatch *b, int s, BPSlab &out)
     out.out_u16 = b->slab[s].out_u16;
     out.code_a = b->slab[s].code_a;
     out.code_b = b->slab[s].code_b;
+    out.sets = b->slab[s].sets;
 }
 
 // Store of voxel `idx` (slab-wide index) from its accumulated sum: v = scale
@@ -351,7 +352,9 @@ __global__ __launch_bounds__(kBPThreads * SL, 4) void bp_sym_kernel(BPBatch arg)
         const int i0 = ty * kTile, j0 = tx * kTile;
         const double xc = j0 + 31.5 - 0.5 * (N - 1);
         const double yc = i0 + 31.5 - 0.5 * (N - 1);
-        const int Np = sl.n_angles, Nc = sl.n_det, H = Np >> 1, M = sl.mirror;
+        // the angle set is `sets` consecutive half-turn sets (a full turn is
+        // two); in each, angle k + H is angle k plus a quarter turn
+        const int Np = sl.n_angles, Nc = sl.n_det, H = (Np / sl.sets) >> 1, M = sl.mirror;
         const int z0 = zg * SL;
         const int nsl = min(SL, sl.n_slices - z0);  // slices present in this group
         // first slice of the group, pinned to a scalar so the row buffer
@@ -367,8 +370,12 @@ __global__ __launch_bounds__(kBPThreads * SL, 4) void bp_sym_kernel(BPBatch arg)
 #pragma unroll
                 for (int p = 0; p < PX; ++p) acc[s][r][p] = 0.0f;
 
-        for (int k0 = 0; k0 < H; k0 += kb) {
-            const int nk = min(kb, H - k0);
+        // stages of up to kb angle pairs k0 .. k0+nk-1 (with k0+H ..); kc
+        // counts pairs over the sets, and a stage never crosses a set
+        for (int kc = 0, nk = 0; kc < sl.sets * H; kc += nk) {
+            const int set = kc / H;
+            const int k0 = kc + set * H;
+            nk = min(kb, (set + 1) * H - kc);
             __syncthreads();
             if (tid < nk) {
                 const double2 cd = sl.csd[k0 + tid];

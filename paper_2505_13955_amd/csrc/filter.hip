@@ -220,16 +220,21 @@ __global__ __launch_bounds__(1024) void filter_kernel(FilterArgs a)
     if (PRE) {
         load_front_end<TI>(z, a, r0, has1, tid, nt);
     } else {
-        const TI *p0 = static_cast<const TI *>(a.in) + r0 * nc;
-        const TI *p1 = p0 + nc;
+        // input rows of in_len samples land on output bins in_first.. (a
+        // wider, virtual detector for offset scans), optionally weighted
+        const int in_len = a.in_len, first = a.in_first;
+        const TI *p0 = static_cast<const TI *>(a.in) + r0 * in_len;
+        const TI *p1 = p0 + in_len;
         // four elements of each row in flight per thread
         for (int n0 = tid; n0 < L; n0 += 4 * nt) {
             float x0[4], x1[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int n = n0 + u * nt;
-                x0[u] = n < nc ? ld_in(p0, n) : 0.0f;
-                x1[u] = (n < nc && has1) ? ld_in(p1, n) : 0.0f;
+                const int m = n0 + u * nt - first;
+                const bool in = (unsigned)m < (unsigned)in_len;
+                const float w = (in && a.weight) ? a.weight[m] : 1.0f;
+                x0[u] = in ? w * ld_in(p0, m) : 0.0f;
+                x1[u] = (in && has1) ? w * ld_in(p1, m) : 0.0f;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)

@@ -35,6 +35,7 @@ struct BPSlab {
     int32_t accumulate;
     int32_t out_u16;           // store clamp(rint(fl(fl(v code_a) + code_b))) as uint16
     float code_a, code_b;
+    int32_t sets;              // symmetric path: half-turn angle sets (2 for a full turn)
 };
 
 struct BPBatch {
@@ -69,8 +70,11 @@ struct PreArgs {
 };
 
 struct FilterArgs {
-    const void *in;    // [rows][Nc] (front end: the projection stack)
+    const void *in;    // [rows][in_len] (front end: the projection stack)
     void *out;         // [rows][Nc]
+    const float *weight;  // [in_len] factors of the input samples, or nullptr
+    int32_t in_first;     // output bin of input sample 0 (input zero elsewhere)
+    int32_t in_len;       // input samples per row
     const float2 *tw;  // [L] exp(-2 pi i e / L)
     const float *H;    // [L] real spectrum / (L * pitch)
     int64_t rows;

@@ -17,6 +17,7 @@ from __future__ import annotations
 import ctypes
 import math
 import os
+import types
 
 import numpy as np
 import torch
@@ -56,12 +57,15 @@ class XctSlab(ctypes.Structure):
         ("n_slices", ctypes.c_int32),
         ("sino", ctypes.c_void_p),
         ("image", ctypes.c_void_p),
+        ("offset_overlap", ctypes.c_double),
     ]
 
 
 EXPORTS = (
     "xct_filter",
     "xct_preprocess_filter",
+    "xct_offset_detector",
+    "xct_filter_offset",
     "xct_backproject",
     "xct_backproject_u16",
     "xct_forward_project",
@@ -93,6 +97,8 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
     sp = ctypes.POINTER(XctSlab)
     sig = {
         "xct_filter": ([gp, i32, vp, i32, vp, i32, i32, vp], ctypes.c_int),
+        "xct_offset_detector": ([gp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "xct_filter_offset": ([gp, i32, vp, i32, vp, i32, i32, ctypes.c_double, vp], ctypes.c_int),
         "xct_preprocess_filter": ([gp, i32, i32, i32, vp, i32, vp, vp, ctypes.c_float, ctypes.c_float,
                                    vp, i32, i32, vp], ctypes.c_int),
         "xct_backproject": ([gp, i32, vp, i32, vp, ctypes.c_float, i32, vp], ctypes.c_int),
@@ -173,6 +179,49 @@ def xct_filter(geom, sino: torch.Tensor, filtered: torch.Tensor, window: str) ->
     _check("xct_filter", rc)
 
 
+def xct_offset_detector(geom) -> tuple[int, float]:
+    """(n_virtual, center_virtual): the mirrored detector an offset scan is
+    filtered and back-projected on."""
+    lib = load_library()
+    g, ang = make_geometry(geom)
+    nv = ctypes.c_int32()
+    cv = ctypes.c_double()
+    _check("xct_offset_detector", lib.xct_offset_detector(ctypes.byref(g), ctypes.byref(nv), ctypes.byref(cv)))
+    return nv.value, cv.value
+
+
+def xct_filter_offset(geom, sino: torch.Tensor, filtered: torch.Tensor, window: str,
+                      overlap: float) -> None:
+    """filtered [S][N_p][n_virtual] = ramp filter of the redundancy-weighted rows
+    of a full-turn offset scan placed on the virtual detector."""
+    lib = load_library()
+    S = _slices(sino, geom, False)
+    nv, _ = xct_offset_detector(geom)
+    p_in = _dev(sino, "sino", DTYPES)
+    p_out = _dev(filtered, "filtered", DTYPES, (S, geom.n_angles, nv))
+    g, ang = make_geometry(geom)
+    rc = lib.xct_filter_offset(ctypes.byref(g), S, p_in, DTYPES[sino.dtype], p_out, DTYPES[filtered.dtype],
+                               WINDOWS[window], float(overlap), _stream(sino))
+    _check("xct_filter_offset", rc)
+
+
+def fbp_offset(sino: torch.Tensor, geom, window: str, overlap: float,
+               filtered_dtype=torch.float32) -> torch.Tensor:
+    """Full-turn offset-scan FBP of sino (S, N_p, N_c): redundancy-weighted
+    filter on the virtual detector, then the back-projection through it with
+    weight 2 pi / N_p."""
+    nv, cv = xct_offset_detector(geom)
+    S = sino.shape[0]
+    q = torch.empty((S, geom.n_angles, nv), dtype=filtered_dtype, device=sino.device)
+    xct_filter_offset(geom, sino, q, window, overlap)
+    virt = types.SimpleNamespace(n_angles=geom.n_angles, n_det=nv, nx=geom.nx, ny=geom.ny,
+                                 det_pitch=geom.det_pitch, pixel_size=geom.pixel_size, center=cv,
+                                 angles=geom.angles)
+    img = torch.empty((S, geom.ny, geom.nx), dtype=torch.float32, device=sino.device)
+    xct_backproject(virt, q, img, 2.0 * math.pi / geom.n_angles, False)
+    return img
+
+
 def xct_preprocess_filter(geom, proj: torch.Tensor, dark: torch.Tensor, flat: torch.Tensor,
                           row_begin: int, filtered: torch.Tensor, window: str, floor: float = 1.0,
                           blur_sigma: float = 0.0) -> None:
@@ -242,7 +291,9 @@ def xct_forward_project(geom, image: torch.Tensor, sino: torch.Tensor, scale: fl
 def _slab_array(slabs):
     arr = (XctSlab * len(slabs))()
     keep = []
-    for i, (geom, sino, image) in enumerate(slabs):
+    for i, slab in enumerate(slabs):
+        geom, sino, image = slab[:3]
+        overlap = float(slab[3]) if len(slab) > 3 else 0.0
         S = _slices(sino, geom, False)
         g, ang = make_geometry(geom)
         keep.append(ang)
@@ -251,11 +302,12 @@ def _slab_array(slabs):
         arr[i].sino = _dev(sino, f"slab {i} sino", DTYPES) if sino is not None else None
         arr[i].image = (_dev(image, f"slab {i} image", (torch.float32,), (S, geom.ny, geom.nx))
                         if image is not None else None)
+        arr[i].offset_overlap = overlap
     return arr, keep
 
 
 def xct_fbp_workspace_bytes(slabs, filtered_dtype=torch.float32) -> int:
-    """slabs: list of (geom, sino, image) (image may be None)."""
+    """slabs: list of (geom, sino, image[, offset_overlap]) (image may be None)."""
     lib = load_library()
     arr, keep = _slab_array(slabs)
     return int(lib.xct_fbp_workspace_bytes(arr, len(slabs), DTYPES[filtered_dtype]))
@@ -263,9 +315,10 @@ def xct_fbp_workspace_bytes(slabs, filtered_dtype=torch.float32) -> int:
 
 def xct_fbp_batch(slabs, window: str, filtered_dtype=torch.float32,
                   workspace: torch.Tensor | None = None) -> None:
-    """image = (pi/N_p) A^T ((1/pitch) h_W * sino) for every slab (geom, sino, image).
-    All sinograms share one dtype.  The workspace (uint8 device tensor) is
-    allocated here when not given."""
+    """image = (pi/N_p) A^T ((1/pitch) h_W * sino) for every slab (geom, sino,
+    image), or the full-turn offset-scan FBP for a slab (geom, sino, image,
+    offset_overlap) with offset_overlap > 0.  All sinograms share one dtype.
+    The workspace (uint8 device tensor) is allocated here when not given."""
     lib = load_library()
     if not slabs:
         raise ValueError("no slabs")

@@ -1,4 +1,4 @@
-"""The five benchmark / parity workloads, as seeded synthetic inputs.
+"""The benchmark / parity workloads, as seeded synthetic inputs.
 
 Each spec mirrors one of the workloads the repository is measured on:
 
@@ -15,6 +15,8 @@ Each spec mirrors one of the workloads the repository is measured on:
 * ``c5``: uneven batch of 24 x 512^2 (720 angles), 12 x 1024^2 (1440), 4 x
   2048^2 (2048), detector width ceil(sqrt(2) N) + 1, BF16 storage, 10 ellipses
   per slice, Poisson noise at 1e4 photons.
+* ``c6``: offset scan, 8 slices of 4096^2, 8192 angles over a full turn, 4096
+  bins with the axis at bin 1024, Hann, the aggregate / void phantom.
 
 Every slice draws its phantom and noise from ``SeedSequence([config, slice])``,
 so any subset of slices can be regenerated on its own.  ``shrink`` builds a
@@ -45,6 +47,7 @@ class SlabSpec:
     noise: tuple = ()  # ("gauss", sigma) | ("poisson", photons) | ()
     storage: str = "f32"
     slice_offset: int = 0  # seed index of the first slice (sub-slabs of a batch)
+    offset_overlap: float = 0.0  # > 0: a full-turn offset scan with this overlap (bins)
 
     @property
     def updates(self) -> int:
@@ -135,6 +138,17 @@ def c5(scale: int = 1) -> list[SlabSpec]:
     return out
 
 
+def c6(n_slices: int = 8) -> SlabSpec:
+    """Offset scan: 8 slices of 4096^2, 8192 angles over a full turn, a 4096-bin
+    detector with the rotation axis at bin 1024 (so the far side reaches 3071
+    bins, past the slice's half-diagonal of 2896), redundancy overlap 1024
+    bins, Hann; the aggregate / void phantom."""
+    n, na = 4096, 8192
+    g = Geometry(n_angles=na, n_det=4096, nx=n, ny=n, center=1024.0,
+                 angles=2.0 * math.pi * np.arange(na) / na)
+    return SlabSpec("c6", 6, g, n_slices, "hann", "aggregate", 200, (), offset_overlap=1024.0)
+
+
 def shrink(spec: SlabSpec, n: int, n_angles: int, n_slices: int) -> SlabSpec:
     """Same recipe at a smaller size: n^2 pixels, n_angles angles, detector
     width scaled with n (centre kept in the same relative place)."""
@@ -145,4 +159,4 @@ def shrink(spec: SlabSpec, n: int, n_angles: int, n_slices: int) -> SlabSpec:
     return dataclasses.replace(spec, geom=_geom(n, n_angles, n_det, center), n_slices=n_slices)
 
 
-ALL = {"c1": c1, "c2": c2, "c3": c3, "c4": c4}
+ALL = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c6": c6}

@@ -128,6 +128,35 @@ def test_preprocess_filter_validation(lib):
     assert f(ctypes.byref(g), 4, 1, 2, FAKE, 3, FAKE, FAKE, 1.0, 1.0, FAKE, 0, 0, None) == EINVAL
 
 
+def test_offset_detector_layout(lib):
+    """Host-only: the virtual detector of an offset scan."""
+    for n_det, center, want in ((60, 14.0, (91, 45.0)), (60, 45.0, (91, 45.0)), (61, 40.5, (82, 40.5)),
+                                (4096, 1024.0, (6143, 3071.0))):
+        g, _ = _geom(n_det=n_det, center=center)
+        nv, cv = ctypes.c_int32(), ctypes.c_double()
+        assert lib.xct_offset_detector(ctypes.byref(g), ctypes.byref(nv), ctypes.byref(cv)) == 0
+        assert (nv.value, cv.value) == want
+    g, _ = _geom(n_det=60, center=14.3)   # 2c not integral
+    nv, cv = ctypes.c_int32(), ctypes.c_double()
+    assert lib.xct_offset_detector(ctypes.byref(g), ctypes.byref(nv), ctypes.byref(cv)) == EINVAL
+    g, _ = _geom(n_det=60, center=-2.0)   # axis off the detector
+    assert lib.xct_offset_detector(ctypes.byref(g), ctypes.byref(nv), ctypes.byref(cv)) == EINVAL
+
+
+def test_filter_offset_validation(lib):
+    g, _ = _geom(n_det=60, center=14.0)
+    f = lib.xct_filter_offset
+    assert f(ctypes.byref(g), 1, FAKE, 0, FAKE2, 0, 0, 0.0, None) == EINVAL      # overlap 0
+    assert f(ctypes.byref(g), 1, FAKE, 0, FAKE2, 0, 0, 14.5, None) == EINVAL     # beyond the short side
+    assert f(ctypes.byref(g), 1, FAKE, 0, FAKE2, 0, 0, float("nan"), None) == EINVAL
+    assert f(ctypes.byref(g), 1, FAKE, 0, FAKE, 0, 0, 10.0, None) == EINVAL      # in place
+    assert f(ctypes.byref(g), 1, FAKE, 5, FAKE2, 0, 0, 10.0, None) == EDTYPE
+    g2, _ = _geom(n_det=60, center=14.25)
+    assert f(ctypes.byref(g2), 1, FAKE, 0, FAKE2, 0, 0, 10.0, None) == EINVAL    # 2c not integral
+    big, _ = _geom(n_det=8192, center=100.0)                                     # 16183 virtual bins
+    assert f(ctypes.byref(big), 1, FAKE, 0, FAKE2, 0, 0, 50.0, None) == ETOOBIG
+
+
 def test_backproject_u16_validation(lib):
     g, _ = _geom()
     f = lib.xct_backproject_u16

@@ -159,6 +159,35 @@ def test_c2_slab_fbp_batch(xct):
         assert err < TOL_F32
 
 
+# ---------------------------------------------------------------- offset scan
+def test_c6_offset_slab_fbp_batch(xct):
+    """8 x 4096^2 offset scan (8192 angles over a full turn, axis at bin 1024 of
+    4096) through xct_fbp_batch as the benchmark launches it; sampled pixels
+    against the oracle's virtual-detector FBP."""
+    spec = configs.c6()
+    g = spec.geom
+    say("c6 generate")
+    p = torch.empty((8, g.n_angles, g.n_det), dtype=torch.float32, device="cuda")
+    for s in range(8):
+        p[s] = spec.sinogram(s, device="cuda").to(torch.float32)
+    img = torch.empty((8, 4096, 4096), dtype=torch.float32, device="cuda")
+    say("c6 fbp")
+    xct.xct_fbp_batch([(g, p, img, spec.offset_overlap)], spec.window)
+    torch.cuda.synchronize()
+    nv, cv, _ = oracle.offset_virtual_detector(g.n_det, g.center)
+    virt = g.replace(n_det=nv, center=cv)
+    rng = np.random.default_rng(6)
+    for s in (0, 5):
+        rows = oracle.offset_rows(p[s].cpu().numpy(), g.n_det, g.center, spec.offset_overlap)
+        q = oracle.filter(rows, g.det_pitch, spec.window)
+        pix = _pixel_sample(rng, 4096, 4096, 2000)
+        pix3 = np.concatenate([np.zeros((len(pix), 1), np.int64), pix], 1)
+        ref = oracle.backproject_pixels(q, virt, pix3, 2.0 * math.pi / g.n_angles)
+        err = rel_l2(img[s].cpu().numpy()[pix[:, 0], pix[:, 1]], ref)
+        say("  slice", s, "rel L2", err)
+        assert err < TOL_F32
+
+
 # ---------------------------------------------------------------- uneven batch
 def test_c5_uneven_batch_one_launch(xct):
     specs = configs.c5()
