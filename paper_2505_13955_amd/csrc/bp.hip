@@ -308,6 +308,27 @@ __device__ __forceinline__ float buf_elem<bf16_t>(__amdgpu_buffer_rsrc_t r, uint
     return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0) << 16);
 }
 
+// Tile of work item t within a slice (group): row-major, or, with
+// XCT_TILE_GROUP = G > 1 and both tile counts divisible by G, row-major over
+// G x G groups of tiles so that consecutive items (which run together on one
+// XCD) cover a compact region and share more detector windows in L2.
+#ifndef XCT_TILE_GROUP
+#define XCT_TILE_GROUP 4
+#endif
+__device__ __forceinline__ void tile_position(int t, int tiles_x, int tiles_y, int &ty, int &tx)
+{
+    constexpr int G = XCT_TILE_GROUP;
+    if (G > 1 && tiles_x % G == 0 && tiles_y % G == 0) {
+        const int grp = t / (G * G), in = t - grp * (G * G);
+        const int gy = grp / (tiles_x / G), gx = grp - gy * (tiles_x / G);
+        ty = gy * G + in / G;
+        tx = gx * G + in % G;
+    } else {
+        ty = t / tiles_x;
+        tx = t - ty * tiles_x;
+    }
+}
+
 // SL slices per work item: every slice of a slab shares the geometry, so the
 // coordinates, floors and LDS addresses of one tile serve all SL slices; only
 // the windows differ.  With SL = 2 the workgroup has 512 threads and each
@@ -347,7 +368,8 @@ __global__ __launch_bounds__(kBPThreads * SL, 4) void bp_sym_kernel(BPBatch arg)
         // pin the results back to scalars)
         const int zg = __builtin_amdgcn_readfirstlane((int)(local / tiles));
         const int t = __builtin_amdgcn_readfirstlane((int)(local - (int64_t)zg * tiles));
-        const int ty = t / sl.tiles_x, tx = t - ty * sl.tiles_x;
+        int ty, tx;
+        tile_position(t, sl.tiles_x, sl.tiles_y, ty, tx);
         const int N = sl.nx, half = N >> 1;
         const int i0 = ty * kTile, j0 = tx * kTile;
         const double xc = j0 + 31.5 - 0.5 * (N - 1);
