@@ -5,19 +5,25 @@
 //   q[n] = (1/pitch) sum_{m=0}^{N_c-1} h_W[n-m] p[m].
 // With the row zero-padded to L >= 2 N_c - 1 and h_W placed circularly, the
 // circular convolution of length L equals the linear one on [0, N_c), so the
-// kernel computes it as IFFT(FFT(p) * H) with H = DFT_L(h_W) precomputed on
+// kernel computes it as IFFT_L(FFT_L(x) H) with H = DFT_L(h_W) precomputed on
 // the host in FP64 (real and even, since h_W is symmetric).
 //
-// Two rows share one complex transform: z = p0 + i p1.  Because H is real,
-// IFFT(FFT(z) H) = q0 + i q1, so one forward and one inverse complex FFT
-// filter two rows with no real-FFT pre/post-processing.  The inverse is done
-// as conj(FFT(conj(Z H))) with the 1/(L pitch) folded into H.
+// One workgroup filters one row.  The real row x of length L = 2M is packed as
+// z[n] = x[2n] + i x[2n+1] and transformed with one complex FFT of length M;
+// a single pass over the bin pairs (k, M - k) recovers the real row's spectrum
+//   X[k] = E + W^k O,  X[M-k] = conj(E - W^k O),  W = exp(-2 pi i / L),
+//   E = (Z[k] + conj Z[M-k]) / 2,  O = (Z[k] - conj Z[M-k]) / 2i,
+// multiplies it by H, and packs Y = H X back into Z'[k] = (Y[k] + conj
+// Y[M-k]) + i (Y[k] - conj Y[M-k]) W^-k, whose inverse FFT of length M holds
+// the filtered row as y[2n] + i y[2n+1].  The factors 1/2 and 1/M and the
+// 1/pitch fold into H / (L pitch).  The inverse is done as the conjugate of
+// the forward transform of conj Z'.
 //
-// The whole transform lives in LDS (L <= 16384 complex FP32 = 128 KiB) and
-// runs as mixed-radix Stockham passes (radix 4, plus one radix-2 pass when
-// log2 L is odd); each pass reads its operands into registers, synchronises,
-// and writes the results in place.  Twiddles exp(-2 pi i e / L) come from a
-// table computed on the host in FP64.
+// The transform lives in LDS (M <= 8192 complex FP32 = 64 KiB, so two
+// workgroups share a CU) and runs as mixed-radix Stockham passes (radix 4,
+// plus one radix-2 pass when log2 M is odd); each pass reads its operands
+// into registers, synchronises, and writes the results in place.  Twiddles
+// come from a table of exp(-2 pi i e / L) computed on the host in FP64.
 #include "xct_internal.h"
 
 namespace xct {
@@ -93,9 +99,11 @@ __device__ __forceinline__ void pass_r2(float2 *z, int L, int Ns, const float2 *
     __syncthreads();
 }
 
-// One radix-4 Stockham pass of span Ns.  The twiddles are fetched before the
-// LDS reads and the barrier, so their latency overlaps both.
-__device__ __forceinline__ void pass_r4(float2 *z, int L, int Ns, const float2 *tw, int tid, int nt)
+// One radix-4 Stockham pass of span Ns over a transform of length L, with
+// twiddles exp(-2 pi i e / L) = tw[e * tws].  The twiddles are fetched before
+// the LDS reads and the barrier, so their latency overlaps both.
+__device__ __forceinline__ void pass_r4(float2 *z, int L, int Ns, const float2 *tw, int tws, int tid,
+                                        int nt)
 {
     float2 v[4][4], w[4][3];
     const int quarter = L >> 2;
@@ -103,7 +111,7 @@ __device__ __forceinline__ void pass_r4(float2 *z, int L, int Ns, const float2 *
     for (int q = 0; q < 4; ++q) {
         const int j = tid + q * nt;
         if (Ns > 1 && j < quarter) {
-            const int e1 = (j & (Ns - 1)) * (quarter / Ns);
+            const int e1 = (j & (Ns - 1)) * (quarter / Ns) * tws;
             w[q][0] = tw[e1];
             w[q][1] = tw[2 * e1];
             w[q][2] = tw[3 * e1];
@@ -143,15 +151,16 @@ __device__ __forceinline__ void pass_r4(float2 *z, int L, int Ns, const float2 *
     __syncthreads();
 }
 
-__device__ __forceinline__ void fft_forward(float2 *z, int L, int log2L, const float2 *tw, int tid,
-                                            int nt)
+// Forward FFT of length L = 2^log2L in place, twiddle table stride tws.
+__device__ __forceinline__ void fft_forward(float2 *z, int L, int log2L, const float2 *tw, int tws,
+                                            int tid, int nt)
 {
     int Ns = 1;
     if (log2L & 1) {
         pass_r2(z, L, 1, tw, tid, nt);
         Ns = 2;
     }
-    for (; Ns < L; Ns <<= 2) pass_r4(z, L, Ns, tw, tid, nt);
+    for (; Ns < L; Ns <<= 2) pass_r4(z, L, Ns, tw, tws, tid, nt);
 }
 
 // Line integral of one raw detector sample (Beer-Lambert, Section V-A c
@@ -161,51 +170,49 @@ __device__ __forceinline__ float beer_lambert(float i, float d, float f, float f
     return -logf(fmaxf(i - d, floor) / fmaxf(f - d, floor));
 }
 
-// Front end of a row pair: rows r0, r0 + 1 of the output are detector row
-// row_begin + s of projection k (r = s N_p + k), read from the projection
-// stack [N_p][n_rows][N_c] with the dark and flat fields of that detector
-// row.  The line integrals are blurred along the channels with the sampled
-// Gaussian (edge samples replicated) staged in the upper half of z, which is
-// zero padding of the transform and holds N_c <= L/2 values.
+// Front end of one row: row r of the output is detector row row_begin + s of
+// projection k (r = s N_p + k), read from the projection stack
+// [N_p][n_rows][N_c] with the dark and flat fields of that detector row.  The
+// line integrals are blurred along the channels with the sampled Gaussian
+// (edge samples replicated); the unblurred row is staged as plain floats in
+// the upper half of the transform buffer (N_c <= L/2 = M floats), which the
+// packed row does not reach before the padding is cleared.
 template <typename TI>
-__device__ __forceinline__ void load_front_end(float2 *z, const FilterArgs &a, int64_t r0, bool has1,
-                                               int tid, int nt)
+__device__ __forceinline__ void load_front_end(float2 *z, const FilterArgs &a, int64_t r, int tid, int nt)
 {
-    const int L = a.L, nc = a.nc;
+    const int L = a.L, M = L >> 1, nc = a.nc;
     const PreArgs &pre = a.pre;
-    const TI *src[2];
-    const float *drow[2], *frow[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int64_t r = has1 || h == 0 ? r0 + h : r0;
-        const int64_t s = r / pre.n_angles, k = r - s * pre.n_angles;
-        const int64_t det_row = pre.row_begin + s;
-        src[h] = static_cast<const TI *>(a.in) + (k * pre.n_rows + det_row) * nc;
-        drow[h] = pre.dark + det_row * nc;
-        frow[h] = pre.flat + det_row * nc;
-    }
-    const int stage = pre.radius > 0 ? (L >> 1) : 0;  // first element of the staged rows
-    for (int n = tid; n < nc; n += nt) {
-        const float p0 = beer_lambert(ld_in(src[0], n), drow[0][n], frow[0][n], pre.floor);
-        const float p1 = has1 ? beer_lambert(ld_in(src[1], n), drow[1][n], frow[1][n], pre.floor) : 0.0f;
-        z[sw(stage + n)] = make_float2(p0, p1);
-    }
-    if (pre.radius > 0) {
+    const int64_t s = r / pre.n_angles, k = r - s * pre.n_angles;
+    const int64_t det_row = pre.row_begin + s;
+    const TI *src = static_cast<const TI *>(a.in) + (k * pre.n_rows + det_row) * nc;
+    const float *drow = pre.dark + det_row * nc, *frow = pre.flat + det_row * nc;
+    const int npk = (nc + 1) >> 1;  // packed elements holding the row
+    if (pre.radius == 0) {
+        for (int n = tid; n < npk; n += nt) {
+            const int j = 2 * n;
+            const float x0 = beer_lambert(ld_in(src, j), drow[j], frow[j], pre.floor);
+            const float x1 = j + 1 < nc ? beer_lambert(ld_in(src, j + 1), drow[j + 1], frow[j + 1], pre.floor)
+                                        : 0.0f;
+            z[sw(n)] = make_float2(x0, x1);
+        }
+    } else {
+        float *stage = reinterpret_cast<float *>(z) + M;
+        for (int j = tid; j < nc; j += nt) stage[j] = beer_lambert(ld_in(src, j), drow[j], frow[j], pre.floor);
         __syncthreads();
         const int R = pre.radius;
-        for (int n = tid; n < nc; n += nt) {
-            float b0 = 0.0f, b1 = 0.0f;
-            for (int m = -R; m <= R; ++m) {
-                const float g = pre.taps[m + R];
-                const float2 v = z[sw(stage + min(max(n + m, 0), nc - 1))];
-                b0 = fmaf(g, v.x, b0);
-                b1 = fmaf(g, v.y, b1);
+        for (int n = tid; n < npk; n += nt) {
+            float b[2] = {0.0f, 0.0f};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int j = 2 * n + h;
+                if (j < nc)
+                    for (int m = -R; m <= R; ++m) b[h] = fmaf(pre.taps[m + R], stage[min(max(j + m, 0), nc - 1)], b[h]);
             }
-            z[sw(n)] = make_float2(b0, b1);
+            z[sw(n)] = make_float2(b[0], b[1]);
         }
-        __syncthreads();
+        __syncthreads();  // the staged row is read before the padding overwrites it
     }
-    for (int n = nc + tid; n < L; n += nt) z[sw(n)] = make_float2(0.0f, 0.0f);
+    for (int n = npk + tid; n < M; n += nt) z[sw(n)] = make_float2(0.0f, 0.0f);
 }
 
 template <typename TI, typename TO, bool PRE>
@@ -213,66 +220,84 @@ __global__ __launch_bounds__(1024) void filter_kernel(FilterArgs a)
 {
     extern __shared__ float2 z[];
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int L = a.L, nc = a.nc;
-    const int64_t r0 = (int64_t)blockIdx.x * 2;
-    const bool has1 = r0 + 1 < a.rows;
+    const int L = a.L, M = L >> 1, nc = a.nc;
+    const int64_t r = blockIdx.x;
 
     if (PRE) {
-        load_front_end<TI>(z, a, r0, has1, tid, nt);
+        load_front_end<TI>(z, a, r, tid, nt);
     } else {
-        // input rows of in_len samples land on output bins in_first.. (a
-        // wider, virtual detector for offset scans), optionally weighted
+        // the row's in_len samples land on output bins in_first.. (a wider,
+        // virtual detector for offset scans), optionally weighted; packed
+        // element n holds bins 2n and 2n + 1; four elements in flight per thread
         const int in_len = a.in_len, first = a.in_first;
-        const TI *p0 = static_cast<const TI *>(a.in) + r0 * in_len;
-        const TI *p1 = p0 + in_len;
-        // four elements of each row in flight per thread
-        for (int n0 = tid; n0 < L; n0 += 4 * nt) {
-            float x0[4], x1[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int m = n0 + u * nt - first;
-                const bool in = (unsigned)m < (unsigned)in_len;
-                const float w = (in && a.weight) ? a.weight[m] : 1.0f;
-                x0[u] = in ? w * ld_in(p0, m) : 0.0f;
-                x1[u] = (in && has1) ? w * ld_in(p1, m) : 0.0f;
-            }
+        const TI *p = static_cast<const TI *>(a.in) + r * in_len;
+        for (int n0 = tid; n0 < M; n0 += 4 * nt) {
+            float x[4][2];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                if (n0 + u * nt < L) z[sw(n0 + u * nt)] = make_float2(x0[u], x1[u]);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int m = 2 * (n0 + u * nt) + h - first;
+                    const bool in = (unsigned)m < (unsigned)in_len;
+                    const float w = (in && a.weight) ? a.weight[m] : 1.0f;
+                    x[u][h] = in ? w * ld_in(p, m) : 0.0f;
+                }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (n0 + u * nt < M) z[sw(n0 + u * nt)] = make_float2(x[u][0], x[u][1]);
         }
     }
     __syncthreads();
-    fft_forward(z, L, a.log2L, a.tw, tid, nt);
-    for (int n = tid; n < L; n += nt) {
-        const float h = a.H[n];
-        const float2 v = z[sw(n)];
-        z[sw(n)] = make_float2(v.x * h, -v.y * h);
+    const int log2M = a.log2L - 1;
+    fft_forward(z, M, log2M, a.tw, 2, tid, nt);
+
+    // spectrum of the real row, times H, packed for the inverse (one thread
+    // per bin pair; k = 0 and k = M/2 pair with themselves and write the same
+    // value twice)
+    for (int k = tid; k <= (M >> 1); k += nt) {
+        const int kk = (M - k) & (M - 1);
+        const float2 Zk = z[sw(k)], Zm = z[sw(kk)];
+        const float2 E = make_float2(0.5f * (Zk.x + Zm.x), 0.5f * (Zk.y - Zm.y));
+        const float2 O = make_float2(0.5f * (Zk.y + Zm.y), 0.5f * (Zm.x - Zk.x));
+        const float2 W = a.tw[k];
+        const float2 WO = cmul(W, O);
+        const float hk = a.H[k], hm = a.H[M - k];
+        const float2 Yk = make_float2(hk * (E.x + WO.x), hk * (E.y + WO.y));    // H X[k]
+        const float2 Ym = make_float2(hm * (E.x - WO.x), -hm * (E.y - WO.y));   // H X[M-k]
+        const float2 P = make_float2(Yk.x + Ym.x, Yk.y - Ym.y);                 // Yk + conj Ym
+        const float2 Q = cmul(make_float2(Yk.x - Ym.x, Yk.y + Ym.y),            // (Yk - conj Ym) W^-k
+                              make_float2(W.x, -W.y));
+        const float2 P2 = make_float2(Ym.x + Yk.x, Ym.y - Yk.y);                // Ym + conj Yk
+        const float2 Q2 = cmul(make_float2(Ym.x - Yk.x, Ym.y + Yk.y),           // (Ym - conj Yk) W^-(M-k)
+                               make_float2(-W.x, -W.y));
+        // conjugates of Z' = P + i Q feed the forward transform that inverts
+        z[sw(k)] = make_float2(P.x - Q.y, -(P.y + Q.x));
+        z[sw(kk)] = make_float2(P2.x - Q2.y, -(P2.y + Q2.x));
     }
     __syncthreads();
-    fft_forward(z, L, a.log2L, a.tw, tid, nt);
+    fft_forward(z, M, log2M, a.tw, 2, tid, nt);
 
-    TO *o0 = static_cast<TO *>(a.out) + r0 * nc;
-    TO *o1 = o0 + nc;
-    for (int n = tid; n < nc; n += nt) {
+    TO *o = static_cast<TO *>(a.out) + r * nc;
+    for (int n = tid; 2 * n < nc; n += nt) {
         const float2 v = z[sw(n)];
-        st_out(o0, n, v.x);
-        if (has1) st_out(o1, n, -v.y);
+        st_out(o, 2 * n, v.x);
+        if (2 * n + 1 < nc) st_out(o, 2 * n + 1, -v.y);
     }
 }
 
 template <typename TI, typename TO, bool PRE>
 static hipError_t launch_typed(const FilterArgs &a, hipStream_t s)
 {
-    const int nt = max(64, min(1024, a.L / 16));
-    const size_t lds = (size_t)a.L * sizeof(float2);
+    const int M = a.L >> 1;
+    const int nt = max(64, min(1024, M / 16));
+    const size_t lds = (size_t)M * sizeof(float2);
     (void)hipGetLastError();  // report only what this launch does
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(filter_kernel<TI, TO, PRE>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    const int64_t pairs = (a.rows + 1) / 2;
-    hipLaunchKernelGGL((filter_kernel<TI, TO, PRE>), dim3((unsigned)pairs), dim3(nt), lds, s, a);
+    hipLaunchKernelGGL((filter_kernel<TI, TO, PRE>), dim3((unsigned)a.rows), dim3(nt), lds, s, a);
     return hipGetLastError();
 }
 
