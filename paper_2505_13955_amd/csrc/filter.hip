@@ -19,11 +19,12 @@
 // 1/pitch fold into H / (L pitch).  The inverse is done as the conjugate of
 // the forward transform of conj Z'.
 //
-// The transform lives in LDS (M <= 8192 complex FP32 = 64 KiB, so two
-// workgroups share a CU) and runs as mixed-radix Stockham passes (radix 4,
+// The transform lives in LDS (M <= 8192 complex FP32 = 64 KiB, plus 8 KiB of
+// twiddles, so two workgroups share a CU) and runs as mixed-radix Stockham passes (radix 4,
 // plus one radix-2 pass when log2 M is odd); each pass reads its operands
 // into registers, synchronises, and writes the results in place.  Twiddles
-// come from a table of exp(-2 pi i e / L) computed on the host in FP64.
+// come from a table of exp(-2 pi i e / L) computed on the host in FP64; the
+// passes read an eighth-turn copy of it held in LDS (M/8 + 1 entries).
 #include "xct_internal.h"
 
 namespace xct {
@@ -99,22 +100,28 @@ __device__ __forceinline__ void pass_r2(float2 *z, int L, int Ns, const float2 *
     __syncthreads();
 }
 
-// One radix-4 Stockham pass of span Ns over a transform of length L, with
-// twiddles exp(-2 pi i e / L) = tw[e * tws].  The twiddles are fetched before
-// the LDS reads and the barrier, so their latency overlaps both.
-__device__ __forceinline__ void pass_r4(float2 *z, int L, int Ns, const float2 *tw, int tws, int tid,
-                                        int nt)
+// exp(-2 pi i e / L) for 0 <= e < L/4 from the eighth-turn table
+// T[e] = exp(-2 pi i e / L), e <= L/8, held in LDS: past an eighth of a turn
+// the cosine and sine swap roles.
+__device__ __forceinline__ float2 twiddle(const float2 *T, int e, int L)
 {
-    float2 v[4][4], w[4][3];
+    const bool low = e <= (L >> 3);
+    const float2 t = T[low ? e : (L >> 2) - e];
+    return low ? t : make_float2(-t.y, -t.x);
+}
+
+// One radix-4 Stockham pass of span Ns over a transform of length L, with
+// twiddles from the LDS eighth-turn table T.  The twiddles are read before
+// the operands and the barrier.
+__device__ __forceinline__ void pass_r4(float2 *z, int L, int Ns, const float2 *T, int tid, int nt)
+{
+    float2 v[4][4], w[4][1];
     const int quarter = L >> 2;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int j = tid + q * nt;
         if (Ns > 1 && j < quarter) {
-            const int e1 = (j & (Ns - 1)) * (quarter / Ns) * tws;
-            w[q][0] = tw[e1];
-            w[q][1] = tw[2 * e1];
-            w[q][2] = tw[3 * e1];
+            w[q][0] = twiddle(T, (j & (Ns - 1)) * (quarter / Ns), L);
         }
     }
 #pragma unroll
@@ -133,9 +140,11 @@ __device__ __forceinline__ void pass_r4(float2 *z, int L, int Ns, const float2 *
             const int k = j & (Ns - 1);
             float2 x0 = v[q][0], x1 = v[q][1], x2 = v[q][2], x3 = v[q][3];
             if (Ns > 1) {
+                // w^2 and w^3 from w: one table read per butterfly
+                const float2 w2 = cmul(w[q][0], w[q][0]);
                 x1 = cmul(x1, w[q][0]);
-                x2 = cmul(x2, w[q][1]);
-                x3 = cmul(x3, w[q][2]);
+                x2 = cmul(x2, w2);
+                x3 = cmul(x3, cmul(w2, w[q][0]));
             }
             const float2 a0 = make_float2(x0.x + x2.x, x0.y + x2.y);
             const float2 a1 = make_float2(x0.x - x2.x, x0.y - x2.y);
@@ -151,16 +160,16 @@ __device__ __forceinline__ void pass_r4(float2 *z, int L, int Ns, const float2 *
     __syncthreads();
 }
 
-// Forward FFT of length L = 2^log2L in place, twiddle table stride tws.
-__device__ __forceinline__ void fft_forward(float2 *z, int L, int log2L, const float2 *tw, int tws,
-                                            int tid, int nt)
+// Forward FFT of length L = 2^log2L in place; T is the eighth-turn twiddle
+// table of length L in LDS.
+__device__ __forceinline__ void fft_forward(float2 *z, int L, int log2L, const float2 *T, int tid, int nt)
 {
     int Ns = 1;
     if (log2L & 1) {
-        pass_r2(z, L, 1, tw, tid, nt);
+        pass_r2(z, L, 1, T, tid, nt);
         Ns = 2;
     }
-    for (; Ns < L; Ns <<= 2) pass_r4(z, L, Ns, tw, tws, tid, nt);
+    for (; Ns < L; Ns <<= 2) pass_r4(z, L, Ns, T, tid, nt);
 }
 
 // Line integral of one raw detector sample (Beer-Lambert, Section V-A c
@@ -222,6 +231,10 @@ __global__ __launch_bounds__(1024) void filter_kernel(FilterArgs a)
     const int tid = threadIdx.x, nt = blockDim.x;
     const int L = a.L, M = L >> 1, nc = a.nc;
     const int64_t r = blockIdx.x;
+    // eighth-turn twiddles of the length-M transform, exp(-2 pi i e / M) =
+    // the length-L table at 2e, after the packed row
+    float2 *T = z + M;
+    for (int e = tid; e <= (M >> 3); e += nt) T[e] = a.tw[2 * e];
 
     if (PRE) {
         load_front_end<TI>(z, a, r, tid, nt);
@@ -249,7 +262,7 @@ __global__ __launch_bounds__(1024) void filter_kernel(FilterArgs a)
     }
     __syncthreads();
     const int log2M = a.log2L - 1;
-    fft_forward(z, M, log2M, a.tw, 2, tid, nt);
+    fft_forward(z, M, log2M, T, tid, nt);
 
     // spectrum of the real row, times H, packed for the inverse (one thread
     // per bin pair; k = 0 and k = M/2 pair with themselves and write the same
@@ -275,7 +288,7 @@ __global__ __launch_bounds__(1024) void filter_kernel(FilterArgs a)
         z[sw(kk)] = make_float2(P2.x - Q2.y, -(P2.y + Q2.x));
     }
     __syncthreads();
-    fft_forward(z, M, log2M, a.tw, 2, tid, nt);
+    fft_forward(z, M, log2M, T, tid, nt);
 
     TO *o = static_cast<TO *>(a.out) + r * nc;
     for (int n = tid; 2 * n < nc; n += nt) {
@@ -290,7 +303,7 @@ static hipError_t launch_typed(const FilterArgs &a, hipStream_t s)
 {
     const int M = a.L >> 1;
     const int nt = max(64, min(1024, M / 16));
-    const size_t lds = (size_t)M * sizeof(float2);
+    const size_t lds = (size_t)(M + M / 8 + 1) * sizeof(float2);  // packed row + twiddles
     (void)hipGetLastError();  // report only what this launch does
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(filter_kernel<TI, TO, PRE>),
