@@ -329,6 +329,10 @@ __device__ __forceinline__ void tile_position(int t, int tiles_x, int tiles_y, i
     }
 }
 
+#ifndef XCT_STAGE_UNITS
+#define XCT_STAGE_UNITS 5  // staging units whose loads are in flight together
+#endif
+
 // SL slices per work item: every slice of a slab shares the geometry, so the
 // coordinates, floors and LDS addresses of one tile serve all SL slices; only
 // the windows differ.  With SL = 2 the workgroup has 512 threads and each
@@ -411,34 +415,65 @@ __global__ __launch_bounds__(kBPThreads * SL, 4) void bp_sym_kernel(BPBatch arg)
             }
             __syncthreads();
             // Each wavefront stages 64 entries of one angle pair of one slice
-            // at a time, so the two rows are wave-uniform buffer resources.  A
-            // slice missing from the last group stages zeros (empty resource).
+            // at a time (a unit), so the two rows are wave-uniform buffer
+            // resources; a slice missing from the last group stages zeros
+            // (empty resource).  The loads of XCT_STAGE_UNITS units are all
+            // issued before the first is used, so a stage waits for one global
+            // latency per group of units rather than one per unit; a unit
+            // past the end loads through an empty resource and stores nothing.
             constexpr int kParts = 2 * W / 64;
+            constexpr int kU = XCT_STAGE_UNITS;
             const int wave = __builtin_amdgcn_readfirstlane(wv);
-            for (int unit = wave; unit < nk * SL * kParts; unit += kThreads / 64) {
-                const int kk = unit / (SL * kParts);
-                const int rest = unit - kk * (SL * kParts);
-                const int s = rest / kParts;
-                const int e = (rest - s * kParts) * 64 + lane;  // entry of the pair, [0, 2W)
-                const int g = e >= W;
-                const int m = e - g * W;
-                const int2 ws = wstart[kk];
-                const int n = (g ? ws.y : ws.x) + m;
-                const int rn = M - n;
-                const T *qs = q + (int64_t)s * Np * Nc;
-                const int len = s < nsl ? Nc : 0;
-                const auto rk = row_rsrc(qs + (int64_t)(k0 + kk) * Nc, len);
-                const auto rh = row_rsrc(qs + (int64_t)(k0 + kk + H) * Nc, len);
-                const uint32_t o0 = elem_offset<T>(n), o1 = elem_offset<T>(n + 1);
-                const uint32_t r0 = elem_offset<T>(rn), r1 = elem_offset<T>(rn - 1);
-                const float f0 = buf_elem<T>(rk, o0), fd = buf_elem<T>(rk, o1) - f0;
-                const float m0 = buf_elem<T>(rk, r0), md = buf_elem<T>(rk, r1) - m0;
-                const float h0 = buf_elem<T>(rh, o0), hd = buf_elem<T>(rh, o1) - h0;
-                const float g0 = buf_elem<T>(rh, r0), gd = buf_elem<T>(rh, r1) - g0;
-                const float mf = -(float)m;
-                float4 *dst = win + kk * PER + s * 4 * W + g * 2 * W + m;
-                dst[0] = make_float4(fmaf(mf, fd, f0), fd, fmaf(mf, md, m0), md);
-                dst[W] = make_float4(fmaf(mf, hd, h0), hd, fmaf(mf, gd, g0), gd);
+            const int nunits = nk * SL * kParts;
+            for (int u0 = wave; u0 < nunits; u0 += kU * (kThreads / 64)) {
+                float v[kU][8];
+                int kkv[kU], sv[kU], gv[kU], mv[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int unit0 = u0 + u * (kThreads / 64);
+                    const bool live = unit0 < nunits;
+                    const int unit = live ? unit0 : u0;
+                    const int kk = unit / (SL * kParts);
+                    const int rest = unit - kk * (SL * kParts);
+                    const int s = rest / kParts;
+                    const int e = (rest - s * kParts) * 64 + lane;  // entry of the pair, [0, 2W)
+                    const int g = e >= W;
+                    const int m = e - g * W;
+                    const int2 ws = wstart[kk];
+                    const int n = (g ? ws.y : ws.x) + m;
+                    const int rn = M - n;
+                    const T *qs = q + (int64_t)s * Np * Nc;
+                    const int len = (live && s < nsl) ? Nc : 0;
+                    const auto rk = row_rsrc(qs + (int64_t)(k0 + kk) * Nc, len);
+                    const auto rh = row_rsrc(qs + (int64_t)(k0 + kk + H) * Nc, len);
+                    const uint32_t o0 = elem_offset<T>(n), o1 = elem_offset<T>(n + 1);
+                    const uint32_t r0 = elem_offset<T>(rn), r1 = elem_offset<T>(rn - 1);
+                    v[u][0] = buf_elem<T>(rk, o0);
+                    v[u][1] = buf_elem<T>(rk, o1);
+                    v[u][2] = buf_elem<T>(rk, r0);
+                    v[u][3] = buf_elem<T>(rk, r1);
+                    v[u][4] = buf_elem<T>(rh, o0);
+                    v[u][5] = buf_elem<T>(rh, o1);
+                    v[u][6] = buf_elem<T>(rh, r0);
+                    v[u][7] = buf_elem<T>(rh, r1);
+                    kkv[u] = kk;
+                    sv[u] = s;
+                    gv[u] = g;
+                    mv[u] = m;
+                }
+                // keep the scheduler from sinking the loads back to their uses
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    if (u0 + u * (kThreads / 64) >= nunits) break;
+                    const float f0 = v[u][0], fd = v[u][1] - f0, m0 = v[u][2], md = v[u][3] - m0;
+                    const float h0 = v[u][4], hd = v[u][5] - h0, g0 = v[u][6], gd = v[u][7] - g0;
+                    const int m = mv[u];
+                    const float mf = -(float)m;
+                    float4 *dst = win + kkv[u] * PER + sv[u] * 4 * W + gv[u] * 2 * W + m;
+                    dst[0] = make_float4(fmaf(mf, fd, f0), fd, fmaf(mf, md, m0), md);
+                    dst[W] = make_float4(fmaf(mf, hd, h0), hd, fmaf(mf, gd, g0), gd);
+                }
             }
             __syncthreads();
             for (int kk = 0; kk < nk; ++kk) {
