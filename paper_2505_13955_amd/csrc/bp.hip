@@ -425,20 +425,23 @@ __global__ __launch_bounds__(kBPThreads * SL, 4) void bp_sym_kernel(BPBatch arg)
             constexpr int kU = XCT_STAGE_UNITS;
             const int wave = __builtin_amdgcn_readfirstlane(wv);
             const int nunits = nk * SL * kParts;
+            // window slot of a unit: angle pair kk, slice s, group g, entry m
+            auto unit_slot = [&](int unit, int &kk, int &s, int &g, int &m) {
+                kk = unit / (SL * kParts);
+                const int rest = unit - kk * (SL * kParts);
+                s = rest / kParts;
+                const int e = (rest - s * kParts) * 64 + lane;  // entry of the pair, [0, 2W)
+                g = e >= W;
+                m = e - g * W;
+            };
             for (int u0 = wave; u0 < nunits; u0 += kU * (kThreads / 64)) {
                 float v[kU][8];
-                int kkv[kU], sv[kU], gv[kU], mv[kU];
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
                     const int unit0 = u0 + u * (kThreads / 64);
                     const bool live = unit0 < nunits;
-                    const int unit = live ? unit0 : u0;
-                    const int kk = unit / (SL * kParts);
-                    const int rest = unit - kk * (SL * kParts);
-                    const int s = rest / kParts;
-                    const int e = (rest - s * kParts) * 64 + lane;  // entry of the pair, [0, 2W)
-                    const int g = e >= W;
-                    const int m = e - g * W;
+                    int kk, s, g, m;
+                    unit_slot(live ? unit0 : u0, kk, s, g, m);
                     const int2 ws = wstart[kk];
                     const int n = (g ? ws.y : ws.x) + m;
                     const int rn = M - n;
@@ -456,21 +459,18 @@ __global__ __launch_bounds__(kBPThreads * SL, 4) void bp_sym_kernel(BPBatch arg)
                     v[u][5] = buf_elem<T>(rh, o1);
                     v[u][6] = buf_elem<T>(rh, r0);
                     v[u][7] = buf_elem<T>(rh, r1);
-                    kkv[u] = kk;
-                    sv[u] = s;
-                    gv[u] = g;
-                    mv[u] = m;
                 }
                 // keep the scheduler from sinking the loads back to their uses
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
                     if (u0 + u * (kThreads / 64) >= nunits) break;
+                    int kk, s, g, m;
+                    unit_slot(u0 + u * (kThreads / 64), kk, s, g, m);
                     const float f0 = v[u][0], fd = v[u][1] - f0, m0 = v[u][2], md = v[u][3] - m0;
                     const float h0 = v[u][4], hd = v[u][5] - h0, g0 = v[u][6], gd = v[u][7] - g0;
-                    const int m = mv[u];
                     const float mf = -(float)m;
-                    float4 *dst = win + kkv[u] * PER + sv[u] * 4 * W + gv[u] * 2 * W + m;
+                    float4 *dst = win + kk * PER + s * 4 * W + g * 2 * W + m;
                     dst[0] = make_float4(fmaf(mf, fd, f0), fd, fmaf(mf, md, m0), md);
                     dst[W] = make_float4(fmaf(mf, hd, h0), hd, fmaf(mf, gd, g0), gd);
                 }
