@@ -387,6 +387,8 @@ __global__ __launch_bounds__(kBPThreads * SL, 4) void bp_sym_kernel(BPBatch arg)
         // resources built from it are wave-uniform
         const T *q = reinterpret_cast<const T *>(
             uniform64(reinterpret_cast<int64_t>(static_cast<const T *>(sl.sino) + (int64_t)z0 * Np * Nc)));
+        const int64_t sl_stride = (int64_t)Np * Nc;  // elements between slices
+        const int64_t h_stride = (int64_t)H * Nc;    // from row k to row k + H
 
         float acc[SL][4][PX];
 #pragma unroll
@@ -423,32 +425,45 @@ __global__ __launch_bounds__(kBPThreads * SL, 4) void bp_sym_kernel(BPBatch arg)
             // past the end loads through an empty resource and stores nothing.
             constexpr int kParts = 2 * W / 64;
             constexpr int kU = XCT_STAGE_UNITS;
+            constexpr int kWaves = kThreads / 64;
+            constexpr int D = SL * kParts;  // units per angle pair
             const int wave = __builtin_amdgcn_readfirstlane(wv);
-            const int nunits = nk * SL * kParts;
-            // window slot of a unit: angle pair kk, slice s, group g, entry m
-            auto unit_slot = [&](int unit, int &kk, int &s, int &g, int &m) {
-                kk = unit / (SL * kParts);
-                const int rest = unit - kk * (SL * kParts);
-                s = rest / kParts;
-                const int e = (rest - s * kParts) * 64 + lane;  // entry of the pair, [0, 2W)
-                g = e >= W;
-                m = e - g * W;
+            const int nunits = nk * D;
+            // Unit u of the stage is angle pair u / D, slice (u % D) / kParts,
+            // part (u % D) % kParts.  A wavefront's units are kWaves apart, so
+            // the pair and remainder advance by scalar adds, and the rows are
+            // addressed from the stage's first row: few scalar instructions
+            // per unit.
+            auto advance = [](int &kk, int &rest, int units) {
+                kk += units / D;
+                rest += units % D;
+                if (rest >= D) {
+                    rest -= D;
+                    ++kk;
+                }
             };
-            for (int u0 = wave; u0 < nunits; u0 += kU * (kThreads / 64)) {
+            const T *qk = q + (int64_t)k0 * Nc;  // row k0 of the group's first slice
+            int kk0 = wave / D, rest0 = wave % D;
+            for (int u0 = wave; u0 < nunits; u0 += kU * kWaves) {
                 float v[kU][8];
+                int kk = kk0, rest = rest0;
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
-                    const int unit0 = u0 + u * (kThreads / 64);
-                    const bool live = unit0 < nunits;
-                    int kk, s, g, m;
-                    unit_slot(live ? unit0 : u0, kk, s, g, m);
-                    const int2 ws = wstart[kk];
+                    // (the buffer resource inputs pinned to scalars, so the
+                    // loads need no waterfall loops)
+                    const bool live = u0 + u * kWaves < nunits;
+                    const int kl = __builtin_amdgcn_readfirstlane(live ? kk : 0);  // dead units: pair 0, empty resource
+                    const int sidx = SL == 1 ? 0 : __builtin_amdgcn_readfirstlane(rest >= kParts);
+                    const int e = (rest - sidx * kParts) * 64 + lane;  // entry of the pair, [0, 2W)
+                    const int g = e >= W, m = e - g * W;
+                    const int2 ws = wstart[kl];
                     const int n = (g ? ws.y : ws.x) + m;
                     const int rn = M - n;
-                    const T *qs = q + (int64_t)s * Np * Nc;
-                    const int len = (live && s < nsl) ? Nc : 0;
-                    const auto rk = row_rsrc(qs + (int64_t)(k0 + kk) * Nc, len);
-                    const auto rh = row_rsrc(qs + (int64_t)(k0 + kk + H) * Nc, len);
+                    const T *row = reinterpret_cast<const T *>(uniform64(
+                        reinterpret_cast<int64_t>(qk + (sidx ? sl_stride : (int64_t)0) + kl * Nc)));
+                    const int len = __builtin_amdgcn_readfirstlane((live && sidx < nsl) ? Nc : 0);
+                    const auto rk = row_rsrc(row, len);
+                    const auto rh = row_rsrc(row + h_stride, len);
                     const uint32_t o0 = elem_offset<T>(n), o1 = elem_offset<T>(n + 1);
                     const uint32_t r0 = elem_offset<T>(rn), r1 = elem_offset<T>(rn - 1);
                     v[u][0] = buf_elem<T>(rk, o0);
@@ -459,21 +474,27 @@ __global__ __launch_bounds__(kBPThreads * SL, 4) void bp_sym_kernel(BPBatch arg)
                     v[u][5] = buf_elem<T>(rh, o1);
                     v[u][6] = buf_elem<T>(rh, r0);
                     v[u][7] = buf_elem<T>(rh, r1);
+                    advance(kk, rest, kWaves);
                 }
                 // keep the scheduler from sinking the loads back to their uses
                 __builtin_amdgcn_sched_barrier(0);
+                kk = kk0;
+                rest = rest0;
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
-                    if (u0 + u * (kThreads / 64) >= nunits) break;
-                    int kk, s, g, m;
-                    unit_slot(u0 + u * (kThreads / 64), kk, s, g, m);
+                    if (u0 + u * kWaves >= nunits) break;
+                    const int sidx = SL == 1 ? 0 : (rest >= kParts);
+                    const int e = (rest - sidx * kParts) * 64 + lane;
+                    const int g = e >= W, m = e - g * W;
                     const float f0 = v[u][0], fd = v[u][1] - f0, m0 = v[u][2], md = v[u][3] - m0;
                     const float h0 = v[u][4], hd = v[u][5] - h0, g0 = v[u][6], gd = v[u][7] - g0;
                     const float mf = -(float)m;
-                    float4 *dst = win + kk * PER + s * 4 * W + g * 2 * W + m;
+                    float4 *dst = win + kk * PER + sidx * 4 * W + g * 2 * W + m;
                     dst[0] = make_float4(fmaf(mf, fd, f0), fd, fmaf(mf, md, m0), md);
                     dst[W] = make_float4(fmaf(mf, hd, h0), hd, fmaf(mf, gd, g0), gd);
+                    advance(kk, rest, kWaves);
                 }
+                advance(kk0, rest0, kU * kWaves);
             }
             __syncthreads();
             for (int kk = 0; kk < nk; ++kk) {
