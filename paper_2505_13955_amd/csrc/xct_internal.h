@@ -105,6 +105,8 @@ struct FPBlock {
 constexpr int kFPAngles = 16;       // angles per block
 constexpr int kFPBins = 256;        // bins per workgroup (one per thread)
 constexpr int kFPLdsFloats = 8192;  // staged image floats per workgroup
+// the stage's cross range is reduced over four corners per angle in one wavefront
+static_assert(4 * kFPAngles <= 64, "angle block larger than one wavefront's corner reduction");
 
 struct FPArgs {
     const float *image;  // [S][Ny][Nx]
