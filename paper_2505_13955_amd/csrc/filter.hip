@@ -66,11 +66,18 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b)
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// LDS position of transform element i: bits 0-3 XORed with bits 3-6.  A
-// permutation within aligned groups of 128 elements that takes the four-way
-// bank conflicts of the span-1 and span-4 passes' strided writes down to at
-// most two-way, with no extra LDS.
-__device__ __forceinline__ int sw(int i) { return i ^ ((i >> 3) & 15); }
+// LDS position of transform element i: with p = bits 5-8 of i, bits 0-4 are
+// XORed with p ^ (p << 1).  A permutation within aligned groups of 32 elements
+// (256 bytes, one pass over the 64 banks) under which every read and write of
+// the radix-16, radix-4 and radix-2 passes (32 lanes of 8-byte elements at a
+// time, transforms of 64 to 16384 points) meets 32 distinct bank pairs; each
+// output bit group the pass strides need is an invertible function of the
+// bits of p that vary across the lanes.  No extra LDS.
+__device__ __forceinline__ int sw(int i)
+{
+    const int p = (i >> 5) & 15;
+    return i ^ p ^ (p << 1);
+}
 
 // One radix-2 Stockham pass of span Ns (only as the first pass, Ns = 1).
 __device__ __forceinline__ void pass_r2(float2 *z, int L, int Ns, const float2 *tw, int tid, int nt)
@@ -160,16 +167,101 @@ __device__ __forceinline__ void pass_r4(float2 *z, int L, int Ns, const float2 *
     __syncthreads();
 }
 
+// Forward radix-4 butterfly in registers: (x0, x1, x2, x3) -> its DFT.
+__device__ __forceinline__ void dft4(float2 &x0, float2 &x1, float2 &x2, float2 &x3)
+{
+    const float2 a0 = make_float2(x0.x + x2.x, x0.y + x2.y);
+    const float2 a1 = make_float2(x0.x - x2.x, x0.y - x2.y);
+    const float2 a2 = make_float2(x1.x + x3.x, x1.y + x3.y);
+    const float2 a3 = make_float2(x1.y - x3.y, x3.x - x1.x);  // -i (x1 - x3)
+    x0 = make_float2(a0.x + a2.x, a0.y + a2.y);
+    x1 = make_float2(a1.x + a3.x, a1.y + a3.y);
+    x2 = make_float2(a0.x - a2.x, a0.y - a2.y);
+    x3 = make_float2(a1.x - a3.x, a1.y - a3.y);
+}
+
+// One radix-16 Stockham pass of span Ns over a transform of length L (one
+// butterfly per thread: L / 16 <= nt).  Operand t of butterfly j is element
+// j + t L/16; it is turned by w^t, w = exp(-2 pi i k / (16 Ns)), k = j mod Ns,
+// with w and w^4 read from the eighth-turn table and the other powers formed
+// by at most three products.  The 16-point DFT runs in registers as four
+// 4-point DFTs over t = 4a + b, the factors exp(-2 pi i b s1 / 16), and four
+// 4-point DFTs over b; output s1 + 4 s2 goes to element (j - k) 16 + k +
+// (s1 + 4 s2) Ns.
+__device__ __forceinline__ void pass_r16(float2 *z, int L, int Ns, const float2 *T, int tid, int nt)
+{
+    const int sixteenth = L >> 4;
+    const int j = tid;
+    const bool on = j < sixteenth;
+    float2 x[16];
+    float2 w1 = make_float2(1.0f, 0.0f), w4 = w1;
+    const int k = j & (Ns - 1);
+    if (on && Ns > 1) {
+        const int e = k * (sixteenth / Ns);
+        w1 = twiddle(T, e, L);
+        w4 = twiddle(T, 4 * e, L);
+    }
+    if (on) {
+#pragma unroll
+        for (int t = 0; t < 16; ++t) x[t] = z[sw(j + t * sixteenth)];
+    }
+    __syncthreads();
+    if (on) {
+        if (Ns > 1) {
+            const float2 w2 = cmul(w1, w1), w3 = cmul(w2, w1);
+            const float2 w8 = cmul(w4, w4), w12 = cmul(w8, w4);
+            const float2 base[4] = {make_float2(1.0f, 0.0f), w4, w8, w12};
+            const float2 fine[3] = {w1, w2, w3};
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                if (a > 0) x[4 * a] = cmul(x[4 * a], base[a]);
+#pragma unroll
+                for (int b = 1; b < 4; ++b) x[4 * a + b] = cmul(x[4 * a + b], a > 0 ? cmul(base[a], fine[b - 1]) : fine[b - 1]);
+            }
+        }
+        // 4-point DFTs over a (t = 4a + b): column b, outputs s1 in place of a
+#pragma unroll
+        for (int b = 0; b < 4; ++b) dft4(x[b], x[4 + b], x[8 + b], x[12 + b]);
+        // factors exp(-2 pi i b s1 / 16) on element (s1, b) = x[4 s1 + b]
+        const float c1 = 0.92387953251128674f;   // cos(pi/8)
+        const float s1c = 0.38268343236508977f;  // sin(pi/8)
+        const float r2 = 0.70710678118654752f;   // cos(pi/4)
+        const float2 f[10] = {make_float2(1.0f, 0.0f), make_float2(c1, -s1c), make_float2(r2, -r2),
+                              make_float2(s1c, -c1), make_float2(0.0f, -1.0f), make_float2(-s1c, -c1),
+                              make_float2(-r2, -r2), make_float2(-c1, -s1c), make_float2(-1.0f, 0.0f),
+                              make_float2(-c1, s1c)};
+#pragma unroll
+        for (int s1 = 1; s1 < 4; ++s1)
+#pragma unroll
+            for (int b = 1; b < 4; ++b) x[4 * s1 + b] = cmul(x[4 * s1 + b], f[b * s1]);
+        // 4-point DFTs over b: row s1, outputs s2
+#pragma unroll
+        for (int s1 = 0; s1 < 4; ++s1) dft4(x[4 * s1], x[4 * s1 + 1], x[4 * s1 + 2], x[4 * s1 + 3]);
+        const int base = ((j - k) << 4) + k;
+#pragma unroll
+        for (int s1 = 0; s1 < 4; ++s1)
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) z[sw(base + (s1 + 4 * s2) * Ns)] = x[4 * s1 + s2];
+    }
+    __syncthreads();
+}
+
 // Forward FFT of length L = 2^log2L in place; T is the eighth-turn twiddle
-// table of length L in LDS.
+// table of length L in LDS.  The factor 2^(log2L mod 4) goes first (radix 2,
+// 4, or 2 then 4), the rest in radix-16 passes.
 __device__ __forceinline__ void fft_forward(float2 *z, int L, int log2L, const float2 *T, int tid, int nt)
 {
     int Ns = 1;
-    if (log2L & 1) {
+    const int lead = log2L & 3;
+    if (lead == 1 || lead == 3) {
         pass_r2(z, L, 1, T, tid, nt);
         Ns = 2;
     }
-    for (; Ns < L; Ns <<= 2) pass_r4(z, L, Ns, T, tid, nt);
+    if (lead >= 2) {
+        pass_r4(z, L, Ns, T, tid, nt);
+        Ns <<= 2;
+    }
+    for (; Ns < L; Ns <<= 4) pass_r16(z, L, Ns, T, tid, nt);
 }
 
 // Line integral of one raw detector sample (Beer-Lambert, Section V-A c
