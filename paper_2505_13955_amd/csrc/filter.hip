@@ -316,6 +316,12 @@ __device__ __forceinline__ void load_front_end(float2 *z, const FilterArgs &a, i
     for (int n = npk + tid; n < M; n += nt) z[sw(n)] = make_float2(0.0f, 0.0f);
 }
 
+// Bin pairs (k, M - k), k = 0 .. M/2, per thread of the spectrum pass: the
+// launch has nt >= M / 16 threads, so M/2 + 1 pairs take at most 9 rounds.
+constexpr int kSpecRounds = 9;
+// Packed elements per thread of the load phase (M / nt <= 16).
+constexpr int kLoadRounds = 16;
+
 template <typename TI, typename TO, bool PRE>
 __global__ __launch_bounds__(1024) void filter_kernel(FilterArgs a)
 {
@@ -323,6 +329,22 @@ __global__ __launch_bounds__(1024) void filter_kernel(FilterArgs a)
     const int tid = threadIdx.x, nt = blockDim.x;
     const int L = a.L, M = L >> 1, nc = a.nc;
     const int64_t r = blockIdx.x;
+
+    // Every global read of the workgroup is issued here, before the first
+    // wait: the row's samples, the twiddle table, and the spectrum pass's
+    // factors H[k], H[M-k] and exp(-2 pi i k / L), which stay in registers
+    // through the first transform.
+    float2 Wk[kSpecRounds];
+    float Hk[kSpecRounds], Hm[kSpecRounds];
+#pragma unroll
+    for (int u = 0; u < kSpecRounds; ++u) {
+        const int k = tid + u * nt;
+        if (k <= (M >> 1)) {
+            Wk[u] = a.tw[k];
+            Hk[u] = a.H[k];
+            Hm[u] = a.H[M - k];
+        }
+    }
     // eighth-turn twiddles of the length-M transform, exp(-2 pi i e / M) =
     // the length-L table at 2e, after the packed row
     float2 *T = z + M;
@@ -333,24 +355,23 @@ __global__ __launch_bounds__(1024) void filter_kernel(FilterArgs a)
     } else {
         // the row's in_len samples land on output bins in_first.. (a wider,
         // virtual detector for offset scans), optionally weighted; packed
-        // element n holds bins 2n and 2n + 1; four elements in flight per thread
+        // element n holds bins 2n and 2n + 1
         const int in_len = a.in_len, first = a.in_first;
         const TI *p = static_cast<const TI *>(a.in) + r * in_len;
-        for (int n0 = tid; n0 < M; n0 += 4 * nt) {
-            float x[4][2];
+        float x[kLoadRounds][2];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < kLoadRounds; ++u)
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int m = 2 * (n0 + u * nt) + h - first;
-                    const bool in = (unsigned)m < (unsigned)in_len;
-                    const float w = (in && a.weight) ? a.weight[m] : 1.0f;
-                    x[u][h] = in ? w * ld_in(p, m) : 0.0f;
-                }
+            for (int h = 0; h < 2; ++h) {
+                const int n = tid + u * nt;
+                const int m = 2 * n + h - first;
+                const bool in = n < M && (unsigned)m < (unsigned)in_len;
+                const float w = (in && a.weight) ? a.weight[m] : 1.0f;
+                x[u][h] = in ? w * ld_in(p, m) : 0.0f;
+            }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (n0 + u * nt < M) z[sw(n0 + u * nt)] = make_float2(x[u][0], x[u][1]);
-        }
+        for (int u = 0; u < kLoadRounds; ++u)
+            if (tid + u * nt < M) z[sw(tid + u * nt)] = make_float2(x[u][0], x[u][1]);
     }
     __syncthreads();
     const int log2M = a.log2L - 1;
@@ -359,14 +380,17 @@ __global__ __launch_bounds__(1024) void filter_kernel(FilterArgs a)
     // spectrum of the real row, times H, packed for the inverse (one thread
     // per bin pair; k = 0 and k = M/2 pair with themselves and write the same
     // value twice)
-    for (int k = tid; k <= (M >> 1); k += nt) {
+#pragma unroll
+    for (int u = 0; u < kSpecRounds; ++u) {
+        const int k = tid + u * nt;
+        if (k > (M >> 1)) break;
         const int kk = (M - k) & (M - 1);
         const float2 Zk = z[sw(k)], Zm = z[sw(kk)];
         const float2 E = make_float2(0.5f * (Zk.x + Zm.x), 0.5f * (Zk.y - Zm.y));
         const float2 O = make_float2(0.5f * (Zk.y + Zm.y), 0.5f * (Zm.x - Zk.x));
-        const float2 W = a.tw[k];
+        const float2 W = Wk[u];
         const float2 WO = cmul(W, O);
-        const float hk = a.H[k], hm = a.H[M - k];
+        const float hk = Hk[u], hm = Hm[u];
         const float2 Yk = make_float2(hk * (E.x + WO.x), hk * (E.y + WO.y));    // H X[k]
         const float2 Ym = make_float2(hm * (E.x - WO.x), -hm * (E.y - WO.y));   // H X[M-k]
         const float2 P = make_float2(Yk.x + Ym.x, Yk.y - Ym.y);                 // Yk + conj Ym
@@ -394,7 +418,7 @@ template <typename TI, typename TO, bool PRE>
 static hipError_t launch_typed(const FilterArgs &a, hipStream_t s)
 {
     const int M = a.L >> 1;
-    const int nt = max(64, min(1024, M / 16));
+    const int nt = max(64, min(1024, M / 16));  // M / nt <= 16 packed elements per thread
     const size_t lds = (size_t)(M + M / 8 + 1) * sizeof(float2);  // packed row + twiddles
     (void)hipGetLastError();  // report only what this launch does
     if (lds > 65536) {
