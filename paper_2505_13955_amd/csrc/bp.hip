@@ -33,7 +33,10 @@
 //    the detector, the coordinates of R^2 Q at th_k and of R^3 Q and R Q at
 //    th_k + pi/2.  One coordinate and one floor then serve four updates,
 //    read from four windows that share one local coordinate.  The workgroup
-//    owns a tile of the top-left quadrant and its three rotations.
+//    owns a tile of the top-left quadrant and its three rotations; with two
+//    slices per work item (512 threads) each thread keeps 8 pixels x 4
+//    rotations x 2 slices, and one 16-byte LDS read (a bin's pair and its
+//    mirror's) serves two updates.
 #include "xct_internal.h"
 
 namespace xct {
