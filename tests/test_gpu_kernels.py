@@ -34,10 +34,10 @@ def _geom(**kw):
 
 # ---------------------------------------------------------------- filter
 @pytest.mark.parametrize("window", ["ram_lak", "shepp_logan", "hann"])
-@pytest.mark.parametrize("nc", [1, 2, 7, 64, 367, 1000, 2900, 8192])
+@pytest.mark.parametrize("nc", [1, 2, 7, 64, 100, 367, 1000, 1500, 2900, 8192])
 def test_filter_matches_oracle(xct, window, nc):
     rng = np.random.default_rng(nc)
-    rows = 5 if nc >= 2900 else 9  # odd: one unpaired row
+    rows = 5 if nc >= 2900 else 9
     p = rng.standard_normal((1, rows, nc)) * 3 + 1
     g = _geom(n_angles=rows, n_det=nc, nx=4, ny=4, det_pitch=0.75)
     say("filter", window, nc)
