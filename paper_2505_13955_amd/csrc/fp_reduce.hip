@@ -173,11 +173,12 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
                 const VT *base = tile + bi;
                 VT s = acc[q];
                 int r = 0;
-                if (p.taps <= 3) {
-                    // hat at most three pixels wide (|A| > 2/3): a fixed
-                    // three-tap body, a few walk steps at a time so their LDS
-                    // reads are in flight together.  A tap past the hat gets
-                    // weight 0 and stays inside the staged width.
+                if (p.taps <= 3 && p.absA <= 1.0f) {
+                    // hat two to three pixels wide (2/3 < |A| <= 1): the taps
+                    // sit at t <= 0, t + 1 (|t + 1| |A| <= 1) and t + 2 > 0
+                    // pixels from the crossing, so their weights need no
+                    // absolute value (first, last) or clamp (middle)
+                    const float c2 = fmaf(-2.0f, p.absA, 1.0f);
                     for (; r + kUnroll <= rc; r += kUnroll) {
                         float t[kUnroll];
                         VT x[kUnroll][3];
@@ -191,11 +192,14 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
                             for (int m = 0; m < 3; ++m) x[u][m] = src[m];
                         }
 #pragma unroll
-                        for (int u = 0; u < kUnroll; ++u)
-#pragma unroll
-                            for (int m = 0; m < 3; ++m)
-                                s = V::fma(fmaxf(fmaf(-p.absA, fabsf(t[u] + (float)m), 1.0f), 0.0f),
-                                           x[u][m], s);
+                        for (int u = 0; u < kUnroll; ++u) {
+                            const float w0 = fmaxf(fmaf(p.absA, t[u], 1.0f), 0.0f);
+                            const float w1 = fmaf(-p.absA, fabsf(t[u] + 1.0f), 1.0f);
+                            const float w2 = fmaxf(fmaf(-p.absA, t[u], c2), 0.0f);
+                            s = V::fma(w0, x[u][0], s);
+                            s = V::fma(w1, x[u][1], s);
+                            s = V::fma(w2, x[u][2], s);
+                        }
                     }
                 }
                 for (; r < rc; ++r) {
