@@ -38,7 +38,7 @@ HBM_PEAK_GBPS = 8000.0
 # rocprofv3 FETCH_SIZE x 2.0 plus WRITE_SIZE x 1.0 (the factors under which a
 # plain 1 GiB device copy reads and writes 1 GiB), from the counter passes in
 # profiles/bp_sym_kernel_slab16_8192.txt.  Valid for that kernel build only.
-BP_TRAFFIC_BYTES = 45_922_600 * 1024 * 2 + 4_195_765 * 1024
+BP_TRAFFIC_BYTES = 45_915_450 * 1024 * 2 + 4_196_195 * 1024
 
 
 def parse():
