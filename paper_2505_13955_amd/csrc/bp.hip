@@ -341,25 +341,28 @@ __device__ __forceinline__ void tile_position(int t, int tiles_x, int tiles_y, i
 // the windows differ.  With SL = 2 the workgroup has 512 threads and each
 // keeps 8 pixels x 4 rotations x 2 slices in registers.
 template <int SL>
-constexpr int sym_threads() { return kBPThreads * SL; }
+constexpr int sym_threads() { return SL == 2 ? XCT_SYM2_THREADS : kBPThreads; }
+template <int SL>
+constexpr int sym_waves() { return SL == 2 ? XCT_SYM2_WAVES : 4; }
 
 template <typename T, int W, int SL>
-__global__ __launch_bounds__(kBPThreads * SL, 4) void bp_sym_kernel(BPBatch arg)
+__global__ __launch_bounds__(sym_threads<SL>(), sym_waves<SL>()) void bp_sym_kernel(BPBatch arg)
 {
     KBatch *b = kernarg_batch();
     extern __shared__ float4 lds4[];
     __shared__ int64_t item_slot;
-    constexpr int kThreads = kBPThreads * SL;
-    constexpr int PX = 16 / SL;          // pixels per thread
-    constexpr int ROWS = 4 / SL;         // lattice rows per thread (stride 16 SL)
+    constexpr int kThreads = sym_threads<SL>();
+    constexpr int PX = 4096 / kThreads;  // pixels per thread
+    constexpr int ROWS = PX / 4;         // lattice rows per thread
+    constexpr int RS = kThreads / 16;    // lattice row stride
     constexpr int PER = 4 * W * SL;      // float4 per angle pair
     const int kb = b->kb;
     float4 *par = lds4;
     int2 *wstart = reinterpret_cast<int2 *>(lds4 + kb);
     float4 *win = lds4 + kb + (kb + 1) / 2;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    // a wave covers an 8 x 8 block, the waves a 16 x 16 SL block; each thread
-    // has pixels (px + 16 a, py + 16 SL c), a < 4, c < ROWS
+    // a wave covers an 8 x 8 block, the waves a 16 x RS block; each thread
+    // has pixels (px + 16 a, py + RS c), a < 4, c < ROWS
     const int px = (lane & 7) | ((wv & 1) << 3);
     const int py = (lane >> 3) | ((wv >> 1) << 3);
     const float dxo = px - 31.5f, dyo = py - 31.5f;
@@ -505,7 +508,7 @@ __global__ __launch_bounds__(kBPThreads * SL, 4) void bp_sym_kernel(BPBatch arg)
                 const float C = p.z, S = p.w;
                 const float4 *wk = win + kk * PER;
                 const float c16 = 16.0f * C, s16 = 16.0f * S;
-                const float cr = 16.0f * SL * C, sr = 16.0f * SL * S;
+                const float cr = (float)RS * C, sr = (float)RS * S;
                 float ua_r = p.x + dxo * C + dyo * S;   // u(Q, th_k) - B_A
                 float ub_r = p.y + dyo * C - dxo * S;   // u(R Q, th_k) - B_B
 #pragma unroll
@@ -542,7 +545,7 @@ __global__ __launch_bounds__(kBPThreads * SL, 4) void bp_sym_kernel(BPBatch arg)
             for (int cc = 0; cc < ROWS; ++cc) {
 #pragma unroll
                 for (int aa = 0; aa < 4; ++aa) {
-                    const int i = i0 + py + 16 * SL * cc, j = j0 + px + 16 * aa;
+                    const int i = i0 + py + RS * cc, j = j0 + px + 16 * aa;
                     if (i < half && j < half) {
                         const int pi = cc * 4 + aa;
                         // Q = (i, j); R Q = (N-1-j, i); R^2 Q = (N-1-i, N-1-j); R^3 Q = (j, N-1-i)

@@ -13,6 +13,12 @@ namespace xct {
 constexpr int kMaxSlabs = 16;
 constexpr int kTile = 64;          // back-projection tile edge (pixels)
 constexpr int kBPThreads = 256;    // back-projection workgroup size
+#ifndef XCT_SYM2_THREADS
+#define XCT_SYM2_THREADS 512  // symmetric kernel, two slices per item: threads per workgroup
+#endif
+#ifndef XCT_SYM2_WAVES
+#define XCT_SYM2_WAVES 4      // wavefronts per SIMD its register budget allows
+#endif
 constexpr int kMaxFFT = 16384;     // largest filter FFT length (LDS resident)
 
 // Storage types of sinogram elements.
