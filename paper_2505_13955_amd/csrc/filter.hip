@@ -107,13 +107,19 @@ __device__ __forceinline__ void pass_r2(float2 *z, int L, int Ns, const float2 *
     __syncthreads();
 }
 
+// LDS position of twiddle-table entry i: bits 0-3 XORed with bits 5-8, a
+// permutation within aligned groups of 32 entries that spreads the table
+// reads of the span-32 radix-16 pass (exponents 16 and 64 entries apart
+// across the lanes) over the banks; consecutive entries stay conflict-free.
+__device__ __forceinline__ int swt(int i) { return i ^ ((i >> 5) & 15); }
+
 // exp(-2 pi i e / L) for 0 <= e < L/4 from the eighth-turn table
 // T[e] = exp(-2 pi i e / L), e <= L/8, held in LDS: past an eighth of a turn
 // the cosine and sine swap roles.
 __device__ __forceinline__ float2 twiddle(const float2 *T, int e, int L)
 {
     const bool low = e <= (L >> 3);
-    const float2 t = T[low ? e : (L >> 2) - e];
+    const float2 t = T[swt(low ? e : (L >> 2) - e)];
     return low ? t : make_float2(-t.y, -t.x);
 }
 
@@ -233,7 +239,9 @@ __device__ __forceinline__ void pass_r16(float2 *z, int L, int Ns, const float2 
 #pragma unroll
         for (int s1 = 1; s1 < 4; ++s1)
 #pragma unroll
-            for (int b = 1; b < 4; ++b) x[4 * s1 + b] = cmul(x[4 * s1 + b], f[b * s1]);
+            for (int b = 1; b < 4; ++b)
+                x[4 * s1 + b] = b * s1 == 4 ? make_float2(x[4 * s1 + b].y, -x[4 * s1 + b].x)  // times -i
+                                            : cmul(x[4 * s1 + b], f[b * s1]);
         // 4-point DFTs over b: row s1, outputs s2
 #pragma unroll
         for (int s1 = 0; s1 < 4; ++s1) dft4(x[4 * s1], x[4 * s1 + 1], x[4 * s1 + 2], x[4 * s1 + 3]);
@@ -303,11 +311,21 @@ __device__ __forceinline__ void load_front_end(float2 *z, const FilterArgs &a, i
         const int R = pre.radius;
         for (int n = tid; n < npk; n += nt) {
             float b[2] = {0.0f, 0.0f};
+            if (2 * n >= R && 2 * n + 1 + R < nc) {
+                // interior: every tap inside the row
+                for (int m = -R; m <= R; ++m) {
+                    const float w = pre.taps[m + R];
+                    b[0] = fmaf(w, stage[2 * n + m], b[0]);
+                    b[1] = fmaf(w, stage[2 * n + 1 + m], b[1]);
+                }
+            } else {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int j = 2 * n + h;
-                if (j < nc)
-                    for (int m = -R; m <= R; ++m) b[h] = fmaf(pre.taps[m + R], stage[min(max(j + m, 0), nc - 1)], b[h]);
+                for (int h = 0; h < 2; ++h) {
+                    const int j = 2 * n + h;
+                    if (j < nc)
+                        for (int m = -R; m <= R; ++m)
+                            b[h] = fmaf(pre.taps[m + R], stage[min(max(j + m, 0), nc - 1)], b[h]);
+                }
             }
             z[sw(n)] = make_float2(b[0], b[1]);
         }
@@ -348,7 +366,7 @@ __global__ __launch_bounds__(1024) void filter_kernel(FilterArgs a)
     // eighth-turn twiddles of the length-M transform, exp(-2 pi i e / M) =
     // the length-L table at 2e, after the packed row
     float2 *T = z + M;
-    for (int e = tid; e <= (M >> 3); e += nt) T[e] = a.tw[2 * e];
+    for (int e = tid; e <= (M >> 3); e += nt) T[swt(e)] = a.tw[2 * e];
 
     if (PRE) {
         load_front_end<TI>(z, a, r, tid, nt);
@@ -419,7 +437,9 @@ static hipError_t launch_typed(const FilterArgs &a, hipStream_t s)
 {
     const int M = a.L >> 1;
     const int nt = max(64, min(1024, M / 16));  // M / nt <= 16 packed elements per thread
-    const size_t lds = (size_t)(M + M / 8 + 1) * sizeof(float2);  // packed row + twiddles
+    // packed row + twiddles (the table rounded up to whole 32-entry groups,
+    // which its swizzle permutes within)
+    const size_t lds = (size_t)(M + ((M / 8 + 1 + 31) & ~31)) * sizeof(float2);
     (void)hipGetLastError();  // report only what this launch does
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(filter_kernel<TI, TO, PRE>),
