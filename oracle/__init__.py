@@ -62,8 +62,15 @@ def _load():
     lib.oracle_backproject_pixels.restype = ctypes.c_int
     lib.oracle_forward.argtypes = geo + [dp, dp]
     lib.oracle_forward.restype = ctypes.c_int
+    lib.oracle_threads.argtypes = []
+    lib.oracle_threads.restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops run on."""
+    return int(_load().oracle_threads())
 
 
 def _f64(a) -> np.ndarray:
@@ -80,6 +87,19 @@ def _geo_args(g):
     ang = _f64(g.angles)
     return ang, (g.n_angles, g.n_det, g.nx, g.ny, float(g.det_pitch), float(g.pixel_size),
                  float(g.center), _ptr(ang))
+
+
+def _workers() -> int:
+    """Threads for scipy's FFT: the CPUs this process may run on, capped by
+    OMP_NUM_THREADS when it is set (the share of a shared host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    if omp.isdigit() and int(omp) > 0:
+        n = min(n, int(omp))
+    return max(n, 1)
 
 
 def kernel_taps(window: str, n: int) -> np.ndarray:
@@ -116,7 +136,7 @@ def filter_fft(p, det_pitch: float, window: str) -> np.ndarray:
     out = np.empty_like(p)
     flat_in = p.reshape(-1, nc)
     flat_out = out.reshape(-1, nc)
-    workers = os.cpu_count() or 1
+    workers = _workers()
     for b in range(0, flat_in.shape[0], 256):
         P = scipy.fft.rfft(flat_in[b:b + 256], n=L, axis=-1, workers=workers)
         P *= H

@@ -105,21 +105,11 @@ def hu_codes(mu, mu_water: float, hu_min: float, hu_max: float) -> np.ndarray:
     return np.clip(np.rint(t), 0, CODE_MAX).astype(np.uint16)
 
 
-def hu_codes_fp32(mu, mu_water: float, hu_min: float, hu_max: float) -> np.ndarray:
-    """The same decision taken in FP32 arithmetic, as the kernel's epilogue
-    takes it: A and B rounded once to FP32, t = fl(fl(mu A) + B), rounded half
-    to even and clipped.  ``mu`` is rounded to FP32 first."""
-    a, b = hu_affine(mu_water, hu_min, hu_max)
-    a32, b32 = np.float32(a), np.float32(b)
-    m32 = np.asarray(mu, dtype=np.float64).astype(np.float32)
-    t = (m32 * a32).astype(np.float32) + b32
-    return np.clip(np.rint(t.astype(np.float32)), 0, CODE_MAX).astype(np.uint16)
-
-
 def hu_rounding_distance(mu, mu_water: float, hu_min: float, hu_max: float) -> np.ndarray:
-    """Distance, in codes, of the FP64 pre-rounding value from the nearest
-    rounding boundary (a half-integer); codes whose value sits closer than the
-    FP32 error of the image to a boundary may round either way."""
+    """Distance, in codes, of the FP64 pre-rounding value A mu + B from the
+    nearest rounding boundary (a half-integer).  A code computed in lower
+    precision can differ from ``hu_codes`` only where this distance is below
+    that computation's error."""
     a, b = hu_affine(mu_water, hu_min, hu_max)
     t = np.asarray(mu, dtype=np.float64) * a + b
     return np.abs(t - np.floor(t) - 0.5)

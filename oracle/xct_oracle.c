@@ -30,6 +30,7 @@
  * [0, N_c) (zero extension, not clamping).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -221,3 +222,15 @@ int oracle_forward(int32_t n_angles, int32_t n_det, int32_t nx, int32_t ny, doub
 }
 
 int oracle_version(void) { return 1; }
+
+/* Threads the OpenMP loops above use (the CPU baseline reports it). */
+int oracle_threads(void)
+{
+    int n = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        n = omp_get_num_threads();
+    }
+    return n;
+}

@@ -50,10 +50,14 @@ def test_taps_sum_to_zero(window):
 
 # ---------------------------------------------------------------- filter
 @pytest.mark.parametrize("window", list(WINDOW_FUNCS))
-@pytest.mark.parametrize("nc", [1, 2, 7, 64, 367, 500])
-def test_filter_fft_route_equals_direct_sum(window, nc):
+@pytest.mark.parametrize("nc,rows", [(1, 5), (2, 5), (7, 5), (64, 5), (367, 5), (500, 5),
+                                     (1449, 300), (2900, 300), (8192, 260)])
+def test_filter_fft_route_equals_direct_sum(window, nc, rows):
+    """The FFT route (zero padding, circular kernel, 256-row batches) equals the
+    direct double sum, also at the workloads' detector widths (1449, 2900 and
+    8192 bins) and over more than one batch of rows."""
     rng = np.random.default_rng(nc)
-    p = rng.standard_normal((5, nc))
+    p = rng.standard_normal((rows, nc)) * 3.0 + 1.0
     q1 = oracle.filter_direct(p, 0.7, window)
     q2 = oracle.filter_fft(p, 0.7, window)
     assert np.abs(q1 - q2).max() <= 1e-12 * max(np.abs(q1).max(), 1e-300)

@@ -132,16 +132,30 @@ def test_hu_rounding_is_half_to_even_and_clipped():
     mu = [2.5, 3.5, 0.49, 0.5, 1.5, 65534.5, 65535.4, 7.0e4, -3.0]
     np.testing.assert_array_equal(pl.hu_codes(mu, 1000.0, -1000.0, 64535.0),
                                   [2, 4, 0, 0, 2, 65534, 65535, 65535, 0])
-    np.testing.assert_array_equal(pl.hu_codes_fp32(mu, 1000.0, -1000.0, 64535.0),
-                                  [2, 4, 0, 0, 2, 65534, 65535, 65535, 0])
 
 
-def test_hu_fp32_decision_agrees_away_from_boundaries():
+def test_hu_rounding_distance_values():
+    """Under the identity map the distance to the nearest half-integer is read
+    off directly: 2.5 sits on a boundary, 2.0 half a code away."""
+    mu = np.array([2.5, 2.0, 2.3, 7.75, -0.5])
+    d = pl.hu_rounding_distance(mu, 1000.0, -1000.0, 64535.0)
+    np.testing.assert_allclose(d, [0.0, 0.5, 0.2, 0.25, 0.0], atol=1e-12)
+
+
+def test_hu_codes_stable_away_from_boundaries():
+    """A value moved by less than its distance to the nearest rounding boundary
+    keeps its code: the property the GPU comparison relies on."""
     rng = np.random.default_rng(6)
     mu = rng.uniform(-0.1, 1.4, 100000)
     args = (0.3, -1000.0, 3000.0)
-    c64 = pl.hu_codes(mu, *args).astype(np.int64)
-    c32 = pl.hu_codes_fp32(mu, *args).astype(np.int64)
-    far = pl.hu_rounding_distance(mu, *args) > 0.05
-    np.testing.assert_array_equal(c32[far], c64[far])
-    assert np.max(np.abs(c32 - c64)) <= 1
+    a, _ = pl.hu_affine(*args)
+    dist = pl.hu_rounding_distance(mu, *args)
+    shift = rng.uniform(-1.0, 1.0, mu.size) * 0.9 * dist / a   # |A shift| < dist
+    np.testing.assert_array_equal(pl.hu_codes(mu + shift, *args), pl.hu_codes(mu, *args))
+    # and a value pushed across its boundary changes code by one
+    t = mu * a + pl.hu_affine(*args)[1]
+    inside = (t > 1) & (t < 65534)
+    frac = t - np.floor(t)
+    push = np.where(frac < 0.5, 0.5 - frac + 1e-6, 0.5 - frac - 1e-6) / a
+    diff = pl.hu_codes(mu + push, *args).astype(np.int64) - pl.hu_codes(mu, *args).astype(np.int64)
+    assert np.all(np.abs(diff[inside]) == 1)
