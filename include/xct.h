@@ -27,9 +27,18 @@
  * except xct_geometry.angles, a HOST array read during the call only.  Work is
  * enqueued on `stream` (a hipStream_t; NULL = the null stream) and the call
  * returns without synchronising; results are visible after the stream syncs.
- * The library keeps one cache of per-geometry device tables (trigonometry,
- * filter spectra), filled on first use with a blocking upload and released by
- * xct_cache_clear(); it allocates nothing else.
+ *
+ * Device tables: the library keeps one cache of per-geometry device tables
+ * (trigonometry, filter spectra, forward-projector plans, blur taps,
+ * redundancy weights), built on the host in FP64.  The first call with a
+ * geometry allocates its tables (hipMalloc, pinned host staging) and uploads
+ * them asynchronously on that call's stream; calls on other streams wait for
+ * the upload through an event.  Later calls with the same geometry allocate
+ * nothing, so a call that is captured into a HIP graph must not be a
+ * geometry's first.  The cache holds at most 256 entries / 1 GiB: past that
+ * the least recently used entries that no call is using are freed, after a
+ * device synchronisation.  xct_cache_clear() frees them all.  The library
+ * allocates nothing else.
  *
  * Errors: every argument is validated before any HIP call and nothing is
  * written when a call returns an error.  Return value 0 = XCT_OK, otherwise a
@@ -47,7 +56,7 @@
 extern "C" {
 #endif
 
-#define XCT_VERSION 10000 /* 1.0.0 */
+#define XCT_VERSION 10100 /* 1.1.0 */
 
 typedef enum {
     XCT_OK = 0,
@@ -84,8 +93,11 @@ typedef struct {
 /* Limits: N_c <= 8192 for the filter (FFT length 2*N_c-1 rounded up to a power
  * of two, at most 16384, held in one workgroup's LDS); N_x, N_y, N_c <= 65536,
  * N_p <= 1 << 20; S * max(N_p*N_c, N_x*N_y) < 2^62; 1/16 <= pixel_size/det_pitch <= 16;
- * |center| <= 1e6; the forward projector takes at most 65535 slices per call.
- * Larger sizes return XCT_ETOOBIG. */
+ * |center| <= 1e6; the forward projector takes at most 65535 slices per call;
+ * a back-projection launch covers fewer than 2^31 work items (64 x 64 tiles
+ * times slices); xct_fbp_batch takes at most 65536 slabs.  Larger sizes
+ * return XCT_ETOOBIG.  Work that needs more than 2^32 work-items in one grid
+ * is split into several launches on the same stream. */
 
 /* Windowed ramp filter of every sinogram row (Section IV-B, first step):
  *   filtered[s][k][n] = (1/det_pitch) sum_{m=0}^{N_c-1} h_W[n-m] sino[s][k][m]
@@ -148,13 +160,12 @@ int xct_preprocess_filter(const xct_geometry *g, int32_t n_rows, int32_t row_beg
                           float floor, float blur_sigma, void *filtered, int32_t filtered_t,
                           int32_t window, xct_stream stream);
 
-/* Back-projection (Section IV-B, second step) and the adjoint of the forward
- * projector:
+/* Back-projection (Section IV-B, second step):
  *   image[s][i][j] = (accumulate ? image[s][i][j] : 0)
  *                    + scale * sum_k sum_n sino[s][k][n] K(u_k(x_j, y_i) - n)
  * Linear interpolation along the detector in FP32; FP16 / BF16 sinograms are
- * widened exactly and everything after is FP32.  FBP uses scale = pi / N_p;
- * the exact transpose of xct_forward_project uses scale = pixel^2 / pitch. */
+ * widened exactly and everything after is FP32.  FBP over a half turn uses
+ * scale = pi / N_p (xct_fbp_batch applies it itself). */
 int xct_backproject(const xct_geometry *g, int32_t n_slices, const void *sino, int32_t sino_t,
                     float *image, float scale, int32_t accumulate, xct_stream stream);
 
@@ -176,15 +187,32 @@ int xct_backproject_u16(const xct_geometry *g, int32_t n_slices, const void *sin
                         uint16_t *image, float scale, double mu_water, double hu_min, double hu_max,
                         xct_stream stream);
 
-/* Pixel-driven forward projector, the exact transpose of the back-projector:
- *   sino[s][k][n] = (accumulate ? sino[s][k][n] : 0)
- *                   + scale * sum_{i,j} image[s][i][j] K(u_k(x_j, y_i) - n)
- * The projector P of the least-squares problem uses scale = pixel^2 / pitch
- * (so that sum_n P x * pitch = sum x * pixel^2); accumulate with a negated
- * scale forms residuals in one pass.  FP32 only.  Deterministic (gather form,
- * no atomics). */
+/* Pixel-driven forward projector P of the least-squares problem, the exact
+ * transpose of the back-projector up to its scale:
+ *   P[(k,n),(i,j)] = (pixel^2 / pitch) K(u_k(x_j, y_i) - n)
+ * (so that sum_n (P x)[k][n] * pitch = sum x * pixel^2 for every angle whose
+ * rays all meet the detector), and
+ *   sino[s][k][n] = (accumulate ? sino[s][k][n] : 0) + alpha (P image[s])[k][n]
+ * with the factor pixel^2 / pitch applied here, in FP64 rounded once into
+ * alpha's FP32 multiplier.  alpha = 1 gives P x; accumulating with alpha = -1
+ * onto a copy of y forms the residual y - P x in one pass.  The paper uses a
+ * forward model only to simulate scans for training data (Section V-B); this
+ * operator is the differentiable pair's forward half.
+ *   image  device [n_slices][N_y][N_x] FP32;  sino  device [n_slices][N_p][N_c] FP32
+ * Deterministic (gather form, no atomics).  Errors: XCT_EINVAL for
+ * non-finite alpha, XCT_ETOOBIG beyond 65535 slices. */
 int xct_forward_project(const xct_geometry *g, int32_t n_slices, const float *image,
-                        float *sino, float scale, int32_t accumulate, xct_stream stream);
+                        float *sino, float alpha, int32_t accumulate, xct_stream stream);
+
+/* Transpose of xct_forward_project (the back-projector scaled by
+ * pixel^2 / pitch), the backward half of the differentiable pair:
+ *   image[s] = (accumulate ? image[s] : 0) + alpha (P^T sino[s])
+ *   sino   device [n_slices][N_p][N_c] FP32;  image  device [n_slices][N_y][N_x] FP32
+ * Same kernels and arithmetic as xct_backproject with
+ * scale = fl32(alpha pixel^2 / pitch).  The least-squares gradient
+ * 2 P^T (P x - y) is alpha = -2 applied to the residual y - P x. */
+int xct_project_adjoint(const xct_geometry *g, int32_t n_slices, const float *sino, float *image,
+                        float alpha, int32_t accumulate, xct_stream stream);
 
 /* One slab of slices sharing a geometry, for xct_fbp_batch. */
 typedef struct {
@@ -208,10 +236,16 @@ size_t xct_fbp_workspace_bytes(const xct_slab *slabs, int32_t n_slabs, int32_t f
  * V-A b):
  *   image = (pi / N_p) A^T ((1/det_pitch) h_W * sino)      per slice
  * The filter runs over every row of every slab into `workspace` (stored as
- * filtered_t), then ONE persistent back-projection launch walks all
- * (slab, slice, tile) work items, largest cost first.  workspace: device,
- * 256-byte aligned, at least xct_fbp_workspace_bytes(); its contents are
- * scratch.  n_slabs <= 16. */
+ * filtered_t), then ONE persistent back-projection launch per kernel variant
+ * (the symmetric kernel for the slabs it serves, with two slices per work
+ * item or, for single-slice slabs, one; the generic kernel for the rest)
+ * walks all (slab, slice, tile) work items, most expensive slab first; the
+ * work counters and the table of slab descriptors also live in the
+ * workspace.  Every work item is computed whole by one workgroup with the
+ * variant a call with its slab alone would use, so the images equal those of
+ * separate calls bit for bit.  workspace: device, 256-byte aligned,
+ * at least xct_fbp_workspace_bytes(); its contents are scratch, and calls
+ * that share a workspace must not overlap.  1 <= n_slabs <= 65536. */
 int xct_fbp_batch(const xct_slab *slabs, int32_t n_slabs, int32_t sino_t, int32_t window,
                   int32_t filtered_t, void *workspace, size_t workspace_bytes,
                   xct_stream stream);

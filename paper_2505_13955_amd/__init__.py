@@ -15,13 +15,12 @@ from .xct import (  # noqa: F401
     XCT_F32,
     XCT_U16,
     XctError,
-    adjoint_scale,
     backproject,
     fbp,
     fbp_offset,
-    fbp_weight,
     filter,
     forward_project,
+    project_adjoint,
     load_library,
     make_geometry,
     xct_backproject,
@@ -33,6 +32,7 @@ from .xct import (  # noqa: F401
     xct_filter,
     xct_filter_offset,
     xct_forward_project,
+    xct_project_adjoint,
     xct_offset_detector,
     xct_preprocess_filter,
     xct_sqdist_f64,

@@ -2,7 +2,7 @@
 exact transpose, the back-projector, as a torch.autograd.Function.
 
     y = project(x, geom)            # P x       (xct_forward_project)
-    y.backward(g)  ->  x.grad = P^T g            (xct_backproject, scale pix^2/pitch)
+    y.backward(g)  ->  x.grad = P^T g            (xct_project_adjoint)
 
 Slices are processed ``chunk`` at a time so that the launches of one call stay
 bounded; ``ls_loss_and_grad`` goes further and streams the least-squares loss
@@ -35,9 +35,8 @@ class XctProject(torch.autograd.Function):
         g = g.contiguous().to(torch.float32)
         S = g.shape[0]
         gx = torch.empty((S, geom.ny, geom.nx), dtype=torch.float32, device=g.device)
-        s = xct.adjoint_scale(geom)
         for s0 in range(0, S, chunk):
-            xct.xct_backproject(geom, g[s0:s0 + chunk], gx[s0:s0 + chunk], s, False)
+            xct.xct_project_adjoint(geom, g[s0:s0 + chunk], gx[s0:s0 + chunk])
         return gx, None, None
 
 
@@ -55,7 +54,6 @@ def ls_loss_and_grad(x: torch.Tensor, y: torch.Tensor, geom, chunk: int = 16):
     x = x.contiguous()
     y = y.contiguous()
     S = x.shape[0]
-    s = xct.adjoint_scale(geom)
     loss = torch.zeros((), dtype=torch.float64, device=x.device)
     grad = torch.empty_like(x)
     res = torch.empty((min(chunk, S), geom.n_angles, geom.n_det), dtype=torch.float32, device=x.device)
@@ -63,7 +61,7 @@ def ls_loss_and_grad(x: torch.Tensor, y: torch.Tensor, geom, chunk: int = 16):
         s1 = min(s0 + chunk, S)
         r = res[: s1 - s0]
         r.copy_(y[s0:s1])
-        xct.xct_forward_project(geom, x[s0:s1], r, -s, accumulate=True)
+        xct.xct_forward_project(geom, x[s0:s1], r, -1.0, accumulate=True)
         loss += xct.xct_dot_f64(r, r)
-        xct.xct_backproject(geom, r, grad[s0:s1], -2.0 * s, False)
+        xct.xct_project_adjoint(geom, r, grad[s0:s1], -2.0)
     return loss, grad

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -59,30 +60,132 @@ int check_slices(const xct_geometry *g, int32_t n_slices)
 }
 
 // ---------------------------------------------------------------- device tables
+//
+// Per-geometry tables (trigonometry, filter spectra, forward-projector plans,
+// blur taps, redundancy weights) are built on the host in FP64 and cached on
+// the device.  One cache entry is one device allocation holding its tables at
+// 256-byte offsets.  Its upload is ordered on the stream of the call that
+// creates it (an asynchronous copy from pinned host staging, kept with the
+// entry), and an event marks its completion so that calls on other streams
+// wait for it.  The cache is bounded: past kCacheEntries entries or
+// kCacheBytes bytes the least recently used entries that no call is using are
+// freed (hipFree, which waits for the device).
 
-struct GeoTables {
-    float2 *cs = nullptr;
-    double2 *csd = nullptr;
-};
+constexpr size_t kCacheBytes = (size_t)1 << 30;
+constexpr size_t kCacheEntries = 256;
 
-struct FilterTables {
-    float2 *tw = nullptr;
-    float *H = nullptr;
-};
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-struct FPTables {
-    FPAngle *ang = nullptr;
-    FPBlock *blocks = nullptr;
+struct Entry {
+    char *dev = nullptr;        // device allocation (all tables of the entry)
+    void *host = nullptr;       // pinned staging of the upload
+    hipEvent_t ready = nullptr; // recorded after the upload, on the creating call's stream
+    bool done = false;          // the upload is known to be complete
+    size_t bytes = 0;
+    uint64_t tick = 0;
+    size_t off[2] = {0, 0};     // offsets of the entry's tables in `dev`
+    // forward-projector plan metadata
     int n_blocks = 0;
-    int rows[2] = {0, 0}, pitch[2] = {0, 0};  // staging shape for 1 and 4 slices per workgroup
+    int rows[2] = {0, 0}, pitch[2] = {0, 0};
+    // filter length
+    int L = 0, lg = 0;
+    template <typename T>
+    T *table(int i) const { return reinterpret_cast<T *>(dev + off[i]); }
 };
+typedef std::shared_ptr<Entry> EntryRef;
 
 std::mutex g_mu;
-std::unordered_map<std::string, GeoTables> g_geo;
-std::unordered_map<std::string, FilterTables> g_filt;
-std::unordered_map<std::string, FPTables> g_fp;
-std::unordered_map<std::string, float *> g_blur;
-std::unordered_map<std::string, float *> g_offset;
+std::unordered_map<std::string, EntryRef> g_cache;
+size_t g_cache_bytes = 0;
+uint64_t g_tick = 0;
+
+void entry_release(Entry &e)
+{
+    if (e.dev) (void)hipFree(e.dev);
+    if (e.host) (void)hipHostFree(e.host);
+    if (e.ready) (void)hipEventDestroy(e.ready);
+    e.dev = nullptr;
+    e.host = nullptr;
+    e.ready = nullptr;
+}
+
+// Evict least recently used entries held by no call until `incoming` more
+// bytes fit (called with g_mu held).
+void cache_make_room(size_t incoming)
+{
+    while (!g_cache.empty() &&
+           (g_cache.size() + 1 > kCacheEntries || g_cache_bytes + incoming > kCacheBytes)) {
+        auto victim = g_cache.end();
+        for (auto it = g_cache.begin(); it != g_cache.end(); ++it)
+            if (it->second.use_count() == 1 && (victim == g_cache.end() || it->second->tick < victim->second->tick))
+                victim = it;
+        if (victim == g_cache.end()) return;  // every entry is in use: grow past the bound
+        (void)hipDeviceSynchronize();         // kernels of earlier calls may still read it
+        g_cache_bytes -= victim->second->bytes;
+        entry_release(*victim->second);
+        g_cache.erase(victim);
+    }
+}
+
+// Look up `key`; on a hit whose upload may still be in flight, make
+// `stream` wait for it.  *out is empty on a miss.  Called with g_mu held.
+int cache_find(const std::string &key, hipStream_t stream, EntryRef *out)
+{
+    auto it = g_cache.find(key);
+    if (it == g_cache.end()) {
+        out->reset();
+        return XCT_OK;
+    }
+    Entry &e = *it->second;
+    e.tick = ++g_tick;
+    if (!e.done) {
+        hipError_t q = hipEventQuery(e.ready);
+        if (q == hipSuccess) {
+            e.done = true;
+        } else if (q == hipErrorNotReady) {
+            hipError_t w = hipStreamWaitEvent(stream, e.ready, 0);
+            if (w != hipSuccess) return hip_fail(w);
+        } else {
+            return hip_fail(q);
+        }
+    }
+    *out = it->second;
+    return XCT_OK;
+}
+
+// Create and upload an entry from host tables `parts` (up to two), ordered on
+// `stream`.  Called with g_mu held.
+int cache_insert(const std::string &key, const void *const parts[2], const size_t sizes[2],
+                 hipStream_t stream, const Entry &meta, EntryRef *out)
+{
+    EntryRef e = std::make_shared<Entry>(meta);
+    size_t total = 0;
+    for (int i = 0; i < 2; ++i) {
+        e->off[i] = total;
+        total += align256(sizes[i]);
+    }
+    total = std::max<size_t>(total, 256);
+    cache_make_room(total);
+    hipError_t r = hipMalloc(reinterpret_cast<void **>(&e->dev), total);
+    if (r == hipSuccess) r = hipHostMalloc(&e->host, total, hipHostMallocDefault);
+    if (r == hipSuccess) {
+        for (int i = 0; i < 2; ++i)
+            if (sizes[i]) std::memcpy(static_cast<char *>(e->host) + e->off[i], parts[i], sizes[i]);
+        r = hipMemcpyAsync(e->dev, e->host, total, hipMemcpyHostToDevice, stream);
+    }
+    if (r == hipSuccess) r = hipEventCreateWithFlags(&e->ready, hipEventDisableTiming);
+    if (r == hipSuccess) r = hipEventRecord(e->ready, stream);
+    if (r != hipSuccess) {
+        entry_release(*e);
+        return hip_fail(r);
+    }
+    e->bytes = total;
+    e->tick = ++g_tick;
+    g_cache.emplace(key, e);
+    g_cache_bytes += total;
+    *out = e;
+    return XCT_OK;
+}
 
 template <typename T>
 void key_append(std::string &k, const T &v)
@@ -96,23 +199,29 @@ int current_device(int *dev)
     return e == hipSuccess ? XCT_OK : hip_fail(e);
 }
 
-// cos/sin of every angle times pixel/pitch, in FP32 (inner loops) and FP64
-// (window anchors), rounded once from FP64 host trigonometry.
-int geo_tables(const xct_geometry *g, GeoTables *out)
+// Key prefix: kind, device.
+int cache_key(char kind, std::string &key)
 {
     int dev;
     if (int rc = current_device(&dev)) return rc;
-    const double r = g->pixel_size / g->det_pitch;
-    std::string key;
+    key.clear();
+    key.push_back(kind);
     key_append(key, dev);
+    return XCT_OK;
+}
+
+// cos/sin of every angle times pixel/pitch, in FP32 (inner loops, table 0) and
+// FP64 (window anchors, table 1), rounded once from FP64 host trigonometry.
+int geo_tables(const xct_geometry *g, hipStream_t stream, EntryRef *out)
+{
+    std::string key;
+    if (int rc = cache_key('g', key)) return rc;
+    const double r = g->pixel_size / g->det_pitch;
     key_append(key, r);
     key.append(reinterpret_cast<const char *>(g->angles), sizeof(double) * g->n_angles);
     std::lock_guard<std::mutex> lock(g_mu);
-    auto it = g_geo.find(key);
-    if (it != g_geo.end()) {
-        *out = it->second;
-        return XCT_OK;
-    }
+    if (int rc = cache_find(key, stream, out)) return rc;
+    if (*out) return XCT_OK;
     const int n = g->n_angles;
     std::vector<float2> cs(n);
     std::vector<double2> csd(n);
@@ -121,36 +230,21 @@ int geo_tables(const xct_geometry *g, GeoTables *out)
         csd[k] = make_double2(c, s);
         cs[k] = make_float2((float)c, (float)s);
     }
-    GeoTables t;
-    hipError_t e = hipMalloc(&t.cs, sizeof(float2) * n);
-    if (e == hipSuccess) e = hipMalloc(&t.csd, sizeof(double2) * n);
-    if (e == hipSuccess) e = hipMemcpy(t.cs, cs.data(), sizeof(float2) * n, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(t.csd, csd.data(), sizeof(double2) * n, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        if (t.cs) (void)hipFree(t.cs);
-        if (t.csd) (void)hipFree(t.csd);
-        return hip_fail(e);
-    }
-    g_geo.emplace(key, t);
-    *out = t;
-    return XCT_OK;
+    const void *parts[2] = {cs.data(), csd.data()};
+    const size_t sizes[2] = {sizeof(float2) * n, sizeof(double2) * n};
+    return cache_insert(key, parts, sizes, stream, Entry(), out);
 }
 
 // Unit-sum sampled Gaussian of standard deviation sigma over -R..R,
-// R = int(4 sigma + 0.5), in FP64 rounded once to FP32, cached on the device.
-int blur_taps(float sigma, int radius, const float **out)
+// R = int(4 sigma + 0.5), in FP64 rounded once to FP32.
+int blur_taps(float sigma, int radius, hipStream_t stream, EntryRef *out)
 {
-    int dev;
-    if (int rc = current_device(&dev)) return rc;
     std::string key;
-    key_append(key, dev);
+    if (int rc = cache_key('b', key)) return rc;
     key_append(key, sigma);
     std::lock_guard<std::mutex> lock(g_mu);
-    auto it = g_blur.find(key);
-    if (it != g_blur.end()) {
-        *out = it->second;
-        return XCT_OK;
-    }
+    if (int rc = cache_find(key, stream, out)) return rc;
+    if (*out) return XCT_OK;
     std::vector<double> g(2 * radius + 1);
     double sum = 0.0;
     for (int m = -radius; m <= radius; ++m) {
@@ -160,16 +254,9 @@ int blur_taps(float sigma, int radius, const float **out)
     }
     std::vector<float> g32(g.size());
     for (size_t i = 0; i < g.size(); ++i) g32[i] = (float)(g[i] / sum);
-    float *d = nullptr;
-    hipError_t e = hipMalloc(&d, sizeof(float) * g32.size());
-    if (e == hipSuccess) e = hipMemcpy(d, g32.data(), sizeof(float) * g32.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        if (d) (void)hipFree(d);
-        return hip_fail(e);
-    }
-    g_blur.emplace(key, d);
-    *out = d;
-    return XCT_OK;
+    const void *parts[2] = {g32.data(), nullptr};
+    const size_t sizes[2] = {sizeof(float) * g32.size(), 0};
+    return cache_insert(key, parts, sizes, stream, Entry(), out);
 }
 
 // Virtual detector of a full-turn scan: the physical bins and their mirror
@@ -196,22 +283,17 @@ void offset_virtual(const xct_geometry *g, int *nv, double *cv, int *first)
 // t = (n - c) / overlap, positive on the detector's longer side,
 // w = 0 (t <= -1), sin^2(pi (1 + t) / 4) (|t| < 1), 1 (t >= 1), so that the
 // two measurements of every ray, bins n and 2c - n half a turn apart, weigh
-// one together.  FP64 on the host, rounded once, cached on the device.
-int offset_weights(const xct_geometry *g, double overlap, const float **out)
+// one together.  FP64 on the host, rounded once.
+int offset_weights(const xct_geometry *g, double overlap, hipStream_t stream, EntryRef *out)
 {
-    int dev;
-    if (int rc = current_device(&dev)) return rc;
     std::string key;
-    key_append(key, dev);
+    if (int rc = cache_key('o', key)) return rc;
     key_append(key, g->n_det);
     key_append(key, g->center);
     key_append(key, overlap);
     std::lock_guard<std::mutex> lock(g_mu);
-    auto it = g_offset.find(key);
-    if (it != g_offset.end()) {
-        *out = it->second;
-        return XCT_OK;
-    }
+    if (int rc = cache_find(key, stream, out)) return rc;
+    if (*out) return XCT_OK;
     const int nc = g->n_det;
     const double side = ((nc - 1) - g->center >= g->center) ? 1.0 : -1.0;
     std::vector<float> w(nc);
@@ -225,16 +307,9 @@ int offset_weights(const xct_geometry *g, double overlap, const float **out)
         }
         w[n] = (float)v;
     }
-    float *d = nullptr;
-    hipError_t e = hipMalloc(&d, sizeof(float) * nc);
-    if (e == hipSuccess) e = hipMemcpy(d, w.data(), sizeof(float) * nc, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        if (d) (void)hipFree(d);
-        return hip_fail(e);
-    }
-    g_offset.emplace(key, d);
-    *out = d;
-    return XCT_OK;
+    const void *parts[2] = {w.data(), nullptr};
+    const size_t sizes[2] = {sizeof(float) * nc, 0};
+    return cache_insert(key, parts, sizes, stream, Entry(), out);
 }
 
 // Checks shared by the offset-scan entry points.
@@ -248,14 +323,12 @@ int check_offset(const xct_geometry *g, double overlap)
     return XCT_OK;
 }
 
-// Forward-projector plan of a geometry (angle table, angle blocks, staging
-// shape), built on the host in FP64 and cached on the device.
-int fp_tables(const xct_geometry *g, FPTables *out)
+// Forward-projector plan of a geometry (angle table 0, angle blocks 1, the
+// staging shapes for one and four slices per workgroup).
+int fp_tables(const xct_geometry *g, hipStream_t stream, EntryRef *out)
 {
-    int dev;
-    if (int rc = current_device(&dev)) return rc;
     std::string key;
-    key_append(key, dev);
+    if (int rc = cache_key('f', key)) return rc;
     key_append(key, g->pixel_size / g->det_pitch);
     key_append(key, g->center);
     key_append(key, g->nx);
@@ -263,33 +336,19 @@ int fp_tables(const xct_geometry *g, FPTables *out)
     key_append(key, g->n_det);
     key.append(reinterpret_cast<const char *>(g->angles), sizeof(double) * g->n_angles);
     std::lock_guard<std::mutex> lock(g_mu);
-    auto it = g_fp.find(key);
-    if (it != g_fp.end()) {
-        *out = it->second;
-        return XCT_OK;
-    }
+    if (int rc = cache_find(key, stream, out)) return rc;
+    if (*out) return XCT_OK;
     std::vector<FPAngle> ang;
     std::vector<FPBlock> blocks;
-    FPTables t;
-    if (int rc = fp_plan(g, ang, blocks, 1, &t.rows[0], &t.pitch[0])) return rc;
+    Entry meta;
+    if (int rc = fp_plan(g, ang, blocks, 1, &meta.rows[0], &meta.pitch[0])) return rc;
     // four slices per workgroup when their staging fits (not for strips many
     // pixels wide)
-    if (fp_plan(g, ang, blocks, 4, &t.rows[1], &t.pitch[1]) != XCT_OK) t.rows[1] = 0;
-    t.n_blocks = (int)blocks.size();
-    hipError_t e = hipMalloc(&t.ang, sizeof(FPAngle) * ang.size());
-    if (e == hipSuccess) e = hipMalloc(&t.blocks, sizeof(FPBlock) * blocks.size());
-    if (e == hipSuccess)
-        e = hipMemcpy(t.ang, ang.data(), sizeof(FPAngle) * ang.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy(t.blocks, blocks.data(), sizeof(FPBlock) * blocks.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        if (t.ang) (void)hipFree(t.ang);
-        if (t.blocks) (void)hipFree(t.blocks);
-        return hip_fail(e);
-    }
-    g_fp.emplace(key, t);
-    *out = t;
-    return XCT_OK;
+    if (fp_plan(g, ang, blocks, 4, &meta.rows[1], &meta.pitch[1]) != XCT_OK) meta.rows[1] = 0;
+    meta.n_blocks = (int)blocks.size();
+    const void *parts[2] = {ang.data(), blocks.data()};
+    const size_t sizes[2] = {sizeof(FPAngle) * ang.size(), sizeof(FPBlock) * blocks.size()};
+    return cache_insert(key, parts, sizes, stream, meta, out);
 }
 
 // Spatial ramp kernel taps h_W[n] (inverse DTFT of |nu| W(nu) on |nu| <= 1/2).
@@ -340,27 +399,22 @@ int fft_length(int nc, int *log2L)
     return L;
 }
 
-// Twiddles exp(-2 pi i e / L) and the filter spectrum H = DFT_L(h_W placed
-// circularly) / (L pitch), both rounded once from FP64.
-int filter_tables(int nc, int window, double pitch, FilterTables *out, int *L_out, int *lg_out)
+// Twiddles exp(-2 pi i e / L) (table 0) and the filter spectrum H =
+// DFT_L(h_W placed circularly) / (L pitch) (table 1), both rounded once from
+// FP64.
+int filter_tables(int nc, int window, double pitch, hipStream_t stream, EntryRef *out)
 {
-    int dev;
-    if (int rc = current_device(&dev)) return rc;
-    int lg;
-    const int L = fft_length(nc, &lg);
     std::string key;
-    key_append(key, dev);
+    if (int rc = cache_key('h', key)) return rc;
     key_append(key, nc);
     key_append(key, window);
     key_append(key, pitch);
-    *L_out = L;
-    *lg_out = lg;
     std::lock_guard<std::mutex> lock(g_mu);
-    auto it = g_filt.find(key);
-    if (it != g_filt.end()) {
-        *out = it->second;
-        return XCT_OK;
-    }
+    if (int rc = cache_find(key, stream, out)) return rc;
+    if (*out) return XCT_OK;
+    Entry meta;
+    const int L = fft_length(nc, &meta.lg);
+    meta.L = L;
     std::vector<std::complex<double>> h(L, 0.0);
     for (long d = -(long)(nc - 1); d <= (long)(nc - 1); ++d)
         h[(size_t)((d % L + L) % L)] = ramp_tap(window, d);
@@ -372,19 +426,9 @@ int filter_tables(int nc, int window, double pitch, FilterTables *out, int *L_ou
         const double ang = 2.0 * M_PI * (double)e / (double)L;
         tw[e] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
     }
-    FilterTables t;
-    hipError_t e = hipMalloc(&t.tw, sizeof(float2) * L);
-    if (e == hipSuccess) e = hipMalloc(&t.H, sizeof(float) * L);
-    if (e == hipSuccess) e = hipMemcpy(t.tw, tw.data(), sizeof(float2) * L, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(t.H, H.data(), sizeof(float) * L, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        if (t.tw) (void)hipFree(t.tw);
-        if (t.H) (void)hipFree(t.H);
-        return hip_fail(e);
-    }
-    g_filt.emplace(key, t);
-    *out = t;
-    return XCT_OK;
+    const void *parts[2] = {tw.data(), H.data()};
+    const size_t sizes[2] = {sizeof(float2) * L, sizeof(float) * L};
+    return cache_insert(key, parts, sizes, stream, meta, out);
 }
 
 int device_cus()
@@ -435,8 +479,8 @@ int symmetric_sets(const xct_geometry *g)
 int choose_path(const xct_geometry *g) { return symmetric_sets(g) ? kPathSymmetric : kPathGeneric; }
 
 struct BPJob {
-    const xct_geometry *g;
-    GeoTables t;
+    const xct_geometry *g;  // geometry the rows are back-projected with
+    EntryRef t;             // its trigonometry tables
     int32_t n_slices;
     const void *sino;
     void *image;
@@ -475,8 +519,12 @@ constexpr size_t kSymStageBytes = 37 * 1024;
 constexpr size_t kSym2StageBytes = XCT_SYM2_STAGE_KB * 1024;
 
 // Launch one back-projection over jobs that all take the same kernel path.
-// counter != nullptr makes it persistent.
-int launch_bp_jobs(std::vector<BPJob> jobs, int dtype, unsigned int *counter, hipStream_t s)
+// `counters` (kXcds zeroed words on the stream) makes it persistent; `table`
+// is device memory for the slab descriptors, needed when there are more than
+// kInlineSlabs jobs.  A non-persistent launch whose grid would exceed 2^32
+// work-items is split into several launches over consecutive item ranges.
+int launch_bp_jobs(std::vector<BPJob> jobs, int dtype, unsigned int *counters, BPSlab *table,
+                   hipStream_t s)
 {
     if (jobs.empty()) return XCT_OK;
     const int path = jobs[0].path;
@@ -487,19 +535,19 @@ int launch_bp_jobs(std::vector<BPJob> jobs, int dtype, unsigned int *counter, hi
     int spi = path == kPathSymmetric ? XCT_SYM_MAX_SLICES : 1;
     for (const BPJob &j : jobs)
         if (j.n_slices < 2) spi = 1;
-    BPBatch b;
-    std::memset(&b, 0, sizeof(b));
+    std::vector<BPSlab> desc(jobs.size());
     int W = 0;
     int64_t items = 0;
     for (size_t i = 0; i < jobs.size(); ++i) {
         const BPJob &j = jobs[i];
-        BPSlab &sl = b.slab[i];
+        BPSlab &sl = desc[i];
+        std::memset(&sl, 0, sizeof(sl));
         int tx, ty;
         const int64_t n_items = plan_tiles(j, spi, &tx, &ty);
         sl.sino = j.sino;
         sl.image = j.image;
-        sl.cs = j.t.cs;
-        sl.csd = j.t.csd;
+        sl.cs = j.t->table<float2>(0);
+        sl.csd = j.t->table<double2>(1);
         sl.center = j.g->center;
         sl.item_begin = items;
         sl.n_angles = j.g->n_angles;
@@ -520,9 +568,11 @@ int launch_bp_jobs(std::vector<BPJob> jobs, int dtype, unsigned int *counter, hi
         W = std::max(W, window_entries(j.g->pixel_size / j.g->det_pitch));
     }
     if (items >= (int64_t)1 << 31) return XCT_ETOOBIG;
+    BPBatch b;
+    std::memset(&b, 0, sizeof(b));
     b.n_slabs = (int32_t)jobs.size();
     b.total_items = items;
-    b.counter = counter;
+    b.counter = counters;
     size_t lds;
     if (path == kPathSymmetric) {
         W = bp_sym_window(W);  // choose_path only routes windows that fit here
@@ -535,20 +585,31 @@ int launch_bp_jobs(std::vector<BPJob> jobs, int dtype, unsigned int *counter, hi
     }
     b.win = W;
     if (lds > 160 * 1024) return XCT_ETOOBIG;
-    int grid;
-    if (counter) {
-        const int per_cu = bp_max_blocks_per_cu(path, dtype, W, spi, lds);
-        grid = (int)std::min<int64_t>(items, (int64_t)per_cu * device_cus());
-        b.xcd_remap = 0;
+    if (jobs.size() > (size_t)kInlineSlabs) {
+        if (!table) return XCT_ETOOBIG;
+        hipError_t e = write_slab_table(table, desc.data(), (int)desc.size(), s);
+        if (e != hipSuccess) return hip_fail(e);
+        b.table = table;
     } else {
-        grid = (int)items;
-        b.xcd_remap = (items % 8 == 0) ? 1 : 0;
+        std::memcpy(b.slab, desc.data(), sizeof(BPSlab) * desc.size());
     }
-    hipError_t e = launch_bp(path, b, dtype, spi, grid, lds, s);
-    return e == hipSuccess ? XCT_OK : hip_fail(e);
+    if (counters) {
+        const int per_cu = bp_max_blocks_per_cu(path, dtype, W, spi, lds);
+        const int grid = (int)std::min<int64_t>(items, (int64_t)per_cu * device_cus());
+        hipError_t e = launch_bp(path, b, dtype, spi, grid, lds, s);
+        return e == hipSuccess ? XCT_OK : hip_fail(e);
+    }
+    const int64_t threads = bp_block_threads(path, spi);
+    const int64_t max_items = ((((int64_t)1 << 32) - 1) / threads) & ~(int64_t)7;
+    for (int64_t base = 0; base < items; base += max_items) {
+        const int64_t count = std::min(max_items, items - base);
+        b.item_base = base;
+        b.xcd_remap = (count % 8 == 0) ? 1 : 0;
+        hipError_t e = launch_bp(path, b, dtype, spi, (int)count, lds, s);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    return XCT_OK;
 }
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
@@ -576,25 +637,9 @@ int xct_last_hip_error(void) { return g_last_hip; }
 void xct_cache_clear(void)
 {
     std::lock_guard<std::mutex> lock(g_mu);
-    for (auto &kv : g_geo) {
-        (void)hipFree(kv.second.cs);
-        (void)hipFree(kv.second.csd);
-    }
-    for (auto &kv : g_filt) {
-        (void)hipFree(kv.second.tw);
-        (void)hipFree(kv.second.H);
-    }
-    for (auto &kv : g_fp) {
-        (void)hipFree(kv.second.ang);
-        (void)hipFree(kv.second.blocks);
-    }
-    for (auto &kv : g_blur) (void)hipFree(kv.second);
-    for (auto &kv : g_offset) (void)hipFree(kv.second);
-    g_offset.clear();
-    g_geo.clear();
-    g_filt.clear();
-    g_fp.clear();
-    g_blur.clear();
+    for (auto &kv : g_cache) entry_release(*kv.second);
+    g_cache.clear();
+    g_cache_bytes = 0;
 }
 
 int xct_filter(const xct_geometry *g, int32_t n_slices, const void *sino, int32_t sino_t,
@@ -607,20 +652,20 @@ int xct_filter(const xct_geometry *g, int32_t n_slices, const void *sino, int32_
     if (window < XCT_RAM_LAK || window > XCT_HANN) return XCT_EDTYPE;
     if (sino == filtered && sino_t != filtered_t) return XCT_EINVAL;
     if (g->n_det > kMaxFFT / 2) return XCT_ETOOBIG;
-    FilterTables ft;
-    int L, lg;
-    if (int rc = filter_tables(g->n_det, window, g->det_pitch, &ft, &L, &lg)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    EntryRef ft;
+    if (int rc = filter_tables(g->n_det, window, g->det_pitch, s, &ft)) return rc;
     FilterArgs a{};
     a.in = sino;
     a.out = filtered;
-    a.tw = ft.tw;
-    a.H = ft.H;
+    a.tw = ft->table<float2>(0);
+    a.H = ft->table<float>(1);
     a.rows = (int64_t)n_slices * g->n_angles;
     a.nc = g->n_det;
     a.in_len = g->n_det;
-    a.L = L;
-    a.log2L = lg;
-    hipError_t e = launch_filter(a, sino_t, filtered_t, (hipStream_t)stream);
+    a.L = ft->L;
+    a.log2L = ft->lg;
+    hipError_t e = launch_filter(a, sino_t, filtered_t, s);
     return e == hipSuccess ? XCT_OK : hip_fail(e);
 }
 
@@ -653,24 +698,23 @@ int xct_filter_offset(const xct_geometry *g, int32_t n_slices, const void *sino,
     double cv;
     offset_virtual(g, &nv, &cv, &first);
     if (nv > kMaxFFT / 2) return XCT_ETOOBIG;
-    FilterTables ft;
-    int L, lg;
-    if (int rc = filter_tables(nv, window, g->det_pitch, &ft, &L, &lg)) return rc;
-    const float *w = nullptr;
-    if (int rc = offset_weights(g, overlap, &w)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    EntryRef ft, w;
+    if (int rc = filter_tables(nv, window, g->det_pitch, s, &ft)) return rc;
+    if (int rc = offset_weights(g, overlap, s, &w)) return rc;
     FilterArgs a{};
     a.in = sino;
     a.out = filtered;
-    a.tw = ft.tw;
-    a.H = ft.H;
-    a.weight = w;
+    a.tw = ft->table<float2>(0);
+    a.H = ft->table<float>(1);
+    a.weight = w->table<float>(0);
     a.in_first = first;
     a.in_len = g->n_det;
     a.rows = (int64_t)n_slices * g->n_angles;
     a.nc = nv;
-    a.L = L;
-    a.log2L = lg;
-    hipError_t e = launch_filter(a, sino_t, filtered_t, (hipStream_t)stream);
+    a.L = ft->L;
+    a.log2L = ft->lg;
+    hipError_t e = launch_filter(a, sino_t, filtered_t, s);
     return e == hipSuccess ? XCT_OK : hip_fail(e);
 }
 
@@ -688,6 +732,7 @@ int xct_preprocess_filter(const xct_geometry *g, int32_t n_rows, int32_t row_beg
     if (!std::isfinite(floor) || !(floor > 0.0f)) return XCT_EINVAL;
     if (!std::isfinite(blur_sigma) || blur_sigma < 0.0f) return XCT_EINVAL;
     if (g->n_det > kMaxFFT / 2) return XCT_ETOOBIG;
+    if ((double)g->n_angles * n_rows * g->n_det > 4.0e18) return XCT_ETOOBIG;
     const int radius = blur_sigma == 0.0f ? 0 : (int)(4.0 * (double)blur_sigma + 0.5);
     if (radius > 64) return XCT_ETOOBIG;
     // the output must not overlap the projection stack
@@ -695,31 +740,50 @@ int xct_preprocess_filter(const xct_geometry *g, int32_t n_rows, int32_t row_beg
     const size_t pbytes = (size_t)g->n_angles * n_rows * g->n_det * dtype_size(proj_t);
     const size_t fbytes = (size_t)n_slices * g->n_angles * g->n_det * dtype_size(filtered_t);
     if (pb < fb + fbytes && fb < pb + pbytes) return XCT_EINVAL;
-    FilterTables ft;
-    int L, lg;
-    if (int rc = filter_tables(g->n_det, window, g->det_pitch, &ft, &L, &lg)) return rc;
-    const float *taps = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    EntryRef ft, taps;
+    if (int rc = filter_tables(g->n_det, window, g->det_pitch, s, &ft)) return rc;
     if (radius > 0)
-        if (int rc = blur_taps(blur_sigma, radius, &taps)) return rc;
+        if (int rc = blur_taps(blur_sigma, radius, s, &taps)) return rc;
     FilterArgs a{};
     a.in = proj;
     a.out = filtered;
-    a.tw = ft.tw;
-    a.H = ft.H;
+    a.tw = ft->table<float2>(0);
+    a.H = ft->table<float>(1);
     a.rows = (int64_t)n_slices * g->n_angles;
     a.nc = g->n_det;
-    a.L = L;
-    a.log2L = lg;
+    a.L = ft->L;
+    a.log2L = ft->lg;
     a.pre.dark = dark;
     a.pre.flat = flat;
-    a.pre.taps = taps;
+    a.pre.taps = taps ? taps->table<float>(0) : nullptr;
     a.pre.radius = radius;
     a.pre.n_rows = n_rows;
     a.pre.row_begin = row_begin;
     a.pre.n_angles = g->n_angles;
     a.pre.floor = floor;
-    hipError_t e = launch_front_end_filter(a, proj_t, filtered_t, (hipStream_t)stream);
+    hipError_t e = launch_front_end_filter(a, proj_t, filtered_t, s);
     return e == hipSuccess ? XCT_OK : hip_fail(e);
+}
+
+// Back-projection of one slab (all entry points but the batch).
+static int backproject_one(const xct_geometry *g, int32_t n_slices, const void *sino, int32_t sino_t,
+                           void *image, float scale, int32_t accumulate, int out_u16, float code_a,
+                           float code_b, hipStream_t s)
+{
+    BPJob j;
+    j.g = g;
+    j.n_slices = n_slices;
+    j.sino = sino;
+    j.image = image;
+    j.scale = scale;
+    j.accumulate = accumulate ? 1 : 0;
+    j.path = choose_path(g);
+    j.out_u16 = out_u16;
+    j.code_a = code_a;
+    j.code_b = code_b;
+    if (int rc = geo_tables(g, s, &j.t)) return rc;
+    return launch_bp_jobs({j}, sino_t, nullptr, nullptr, s);
 }
 
 int xct_backproject(const xct_geometry *g, int32_t n_slices, const void *sino, int32_t sino_t,
@@ -730,16 +794,8 @@ int xct_backproject(const xct_geometry *g, int32_t n_slices, const void *sino, i
     if (!sino || !image) return XCT_EINVAL;
     if (!dtype_ok(sino_t)) return XCT_EDTYPE;
     if (!std::isfinite(scale)) return XCT_EINVAL;
-    BPJob j;
-    j.g = g;
-    j.n_slices = n_slices;
-    j.sino = sino;
-    j.image = image;
-    j.scale = scale;
-    j.accumulate = accumulate ? 1 : 0;
-    j.path = choose_path(g);
-    if (int rc = geo_tables(g, &j.t)) return rc;
-    return launch_bp_jobs({j}, sino_t, nullptr, (hipStream_t)stream);
+    return backproject_one(g, n_slices, sino, sino_t, image, scale, accumulate, 0, 0.0f, 0.0f,
+                           (hipStream_t)stream);
 }
 
 int xct_backproject_u16(const xct_geometry *g, int32_t n_slices, const void *sino, int32_t sino_t,
@@ -759,52 +815,56 @@ int xct_backproject_u16(const xct_geometry *g, int32_t n_slices, const void *sin
     const double B = (-1000.0 - hu_min) * span;
     const float a32 = (float)A, b32 = (float)B;
     if (!std::isfinite(a32) || !std::isfinite(b32)) return XCT_EINVAL;
-    BPJob j;
-    j.g = g;
-    j.n_slices = n_slices;
-    j.sino = sino;
-    j.image = image;
-    j.scale = scale;
-    j.accumulate = 0;
-    j.path = choose_path(g);
-    j.out_u16 = 1;
-    j.code_a = a32;
-    j.code_b = b32;
-    if (int rc = geo_tables(g, &j.t)) return rc;
-    return launch_bp_jobs({j}, sino_t, nullptr, (hipStream_t)stream);
+    return backproject_one(g, n_slices, sino, sino_t, image, scale, 0, 1, a32, b32,
+                           (hipStream_t)stream);
 }
 
+// P = (pixel^2 / pitch) A, the projector of the least-squares problem.
+static double projector_scale(const xct_geometry *g) { return g->pixel_size * g->pixel_size / g->det_pitch; }
+
 int xct_forward_project(const xct_geometry *g, int32_t n_slices, const float *image, float *sino,
-                        float scale, int32_t accumulate, xct_stream stream)
+                        float alpha, int32_t accumulate, xct_stream stream)
 {
     if (int rc = check_geometry(g, true)) return rc;
     if (int rc = check_slices(g, n_slices)) return rc;
     if (!image || !sino) return XCT_EINVAL;
-    if (!std::isfinite(scale)) return XCT_EINVAL;
+    if (!std::isfinite(alpha)) return XCT_EINVAL;
     if (n_slices > 65535) return XCT_ETOOBIG;
-    FPTables t;
-    if (int rc = fp_tables(g, &t)) return rc;
-    FPArgs a;
+    hipStream_t s = (hipStream_t)stream;
+    EntryRef t;
+    if (int rc = fp_tables(g, s, &t)) return rc;
+    FPArgs a{};
     a.image = image;
     a.sino = sino;
-    a.ang = t.ang;
-    a.blocks = t.blocks;
-    a.n_blocks = t.n_blocks;
+    a.ang = t->table<FPAngle>(0);
+    a.blocks = t->table<FPBlock>(1);
+    a.n_blocks = t->n_blocks;
     a.bin_blocks = (g->n_det + kFPBins - 1) / kFPBins;
     // four slices per workgroup share coordinates and weights; a call with
     // one or two slices keeps one per workgroup
-    const int sl = (n_slices >= 3 && t.rows[1] > 0) ? 4 : 1;
-    a.rows = t.rows[sl == 4];
-    a.pitch = t.pitch[sl == 4];
-    a.scale = scale;
+    const int sl = (n_slices >= 3 && t->rows[1] > 0) ? 4 : 1;
+    a.rows = t->rows[sl == 4];
+    a.pitch = t->pitch[sl == 4];
+    a.scale = (float)((double)alpha * projector_scale(g));
     a.accumulate = accumulate ? 1 : 0;
     a.n_angles = g->n_angles;
     a.n_det = g->n_det;
     a.nx = g->nx;
     a.ny = g->ny;
     a.n_slices = n_slices;
-    hipError_t e = launch_forward(a, sl, (hipStream_t)stream);
+    hipError_t e = launch_forward(a, sl, s);
     return e == hipSuccess ? XCT_OK : hip_fail(e);
+}
+
+int xct_project_adjoint(const xct_geometry *g, int32_t n_slices, const float *sino, float *image,
+                        float alpha, int32_t accumulate, xct_stream stream)
+{
+    if (int rc = check_geometry(g, true)) return rc;
+    if (int rc = check_slices(g, n_slices)) return rc;
+    if (!sino || !image) return XCT_EINVAL;
+    if (!std::isfinite(alpha)) return XCT_EINVAL;
+    return backproject_one(g, n_slices, sino, XCT_F32, image, (float)((double)alpha * projector_scale(g)),
+                           accumulate, 0, 0.0f, 0.0f, (hipStream_t)stream);
 }
 
 // Detector bins of a slab's filtered rows: the virtual (mirrored) detector
@@ -833,10 +893,15 @@ static int check_slabs(const xct_slab *slabs, int32_t n_slabs, bool need_data)
     return XCT_OK;
 }
 
+// Workspace layout of xct_fbp_batch: 256 bytes of work counters (kXcds per
+// launch group), the slab descriptor table, then the filtered rows of every
+// slab, each region 256-byte aligned.
+static size_t table_bytes(int32_t n_slabs) { return align256(sizeof(BPSlab) * (size_t)n_slabs); }
+
 size_t xct_fbp_workspace_bytes(const xct_slab *slabs, int32_t n_slabs, int32_t filtered_t)
 {
     if (check_slabs(slabs, n_slabs, false) || !dtype_ok(filtered_t)) return 0;
-    size_t bytes = 256;  // work counters
+    size_t bytes = 256 + table_bytes(n_slabs);
     for (int i = 0; i < n_slabs; ++i) {
         const xct_geometry &g = slabs[i].geom;
         bytes += align256((size_t)slabs[i].n_slices * g.n_angles * filtered_bins(slabs[i]) *
@@ -848,6 +913,7 @@ size_t xct_fbp_workspace_bytes(const xct_slab *slabs, int32_t n_slabs, int32_t f
 int xct_fbp_batch(const xct_slab *slabs, int32_t n_slabs, int32_t sino_t, int32_t window,
                   int32_t filtered_t, void *workspace, size_t workspace_bytes, xct_stream stream)
 {
+    static_assert(3 * kXcds * sizeof(unsigned int) <= 256, "work counters exceed their region");
     if (int rc = check_slabs(slabs, n_slabs, true)) return rc;
     if (!dtype_ok(sino_t) || !dtype_ok(filtered_t)) return XCT_EDTYPE;
     if (window < XCT_RAM_LAK || window > XCT_HANN) return XCT_EDTYPE;
@@ -857,8 +923,14 @@ int xct_fbp_batch(const xct_slab *slabs, int32_t n_slabs, int32_t sino_t, int32_
 
     char *ws = static_cast<char *>(workspace);
     unsigned int *counters = reinterpret_cast<unsigned int *>(ws);
-    size_t off = 256;
-    std::vector<BPJob> jobs_by_path[2];
+    BPSlab *table = reinterpret_cast<BPSlab *>(ws + 256);
+    size_t off = 256 + table_bytes(n_slabs);
+    // Launch groups: the generic kernel; the symmetric kernel with one slice
+    // per item (single-slice slabs); the symmetric kernel with two slices per
+    // item.  A slab takes the kernel variant a call with that slab alone
+    // takes, so the images equal separate calls bit for bit.
+    enum { kGroupGeneric = 0, kGroupSym1 = 1, kGroupSym2 = 2, kGroups = 3 };
+    std::vector<BPJob> groups[kGroups];
     // back-projection geometry of offset slabs (virtual detector); lives until
     // the launches below have read it
     std::vector<xct_geometry> virt(n_slabs);
@@ -890,13 +962,22 @@ int xct_fbp_batch(const xct_slab *slabs, int32_t n_slabs, int32_t sino_t, int32_
         j.scale = (float)weight;
         j.accumulate = 0;
         j.path = choose_path(g);
-        if (int rc = geo_tables(g, &j.t)) return rc;
-        jobs_by_path[j.path].push_back(j);
+        if (int rc = geo_tables(g, s, &j.t)) return rc;
+        const int grp = j.path == kPathGeneric ? kGroupGeneric : (j.n_slices >= 2 ? kGroupSym2 : kGroupSym1);
+        groups[grp].push_back(j);
     }
-    hipError_t e = launch_fill_u32(counters, 2, 0u, s);
+    hipError_t e = launch_fill_u32(counters, kGroups * kXcds, 0u, s);
     if (e != hipSuccess) return hip_fail(e);
-    for (int p = kPathSymmetric; p >= kPathGeneric; --p)
-        if (int rc = launch_bp_jobs(jobs_by_path[p], filtered_t, counters + p, s)) return rc;
+    // each group reads its descriptors from its own part of the table
+    BPSlab *group_table[kGroups];
+    size_t first = 0;
+    for (int grp = kGroups - 1; grp >= 0; --grp) {
+        group_table[grp] = table + first;
+        first += groups[grp].size();
+    }
+    for (int grp = kGroups - 1; grp >= 0; --grp)
+        if (int rc = launch_bp_jobs(groups[grp], filtered_t, counters + grp * kXcds, group_table[grp], s))
+            return rc;
     return XCT_OK;
 }
 

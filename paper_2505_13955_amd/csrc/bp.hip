@@ -37,6 +37,8 @@
 //    slices per work item (512 threads) each thread keeps 8 pixels x 4
 //    rotations x 2 slices, and one 16-byte LDS read (a bin's pair and its
 //    mirror's) serves two updates.
+#include <cstring>
+
 #include "xct_internal.h"
 
 namespace xct {
@@ -64,36 +66,48 @@ __device__ __forceinline__ float row_elem(const T *row, int n, int nc)
 // of the kernarg segment.  Reading it through a constant-address-space
 // pointer to that segment keeps the dynamically indexed slab table in scalar
 // loads: every field read from it is wave-uniform (an SGPR), as are the rows
-// and buffer resources derived from it, and nothing is copied to scratch.
+// and buffer resources derived from it, and nothing is copied to scratch.  A
+// launch over more slabs than the arguments hold reads the descriptors from
+// a device table through the same (constant) address space, which also keeps
+// them in scalar loads (the table is written by an earlier launch on the same
+// stream, and every launch starts with the scalar cache invalidated).
 typedef const __attribute__((address_space(4))) BPBatch KBatch;
+typedef const __attribute__((address_space(4))) BPSlab KSlab;
 
 __device__ __forceinline__ KBatch *kernarg_batch()
 {
     return (KBatch *)__builtin_amdgcn_kernarg_segment_ptr();
 }
 
+__device__ __forceinline__ KSlab *slab_at(KBatch *b, int s)
+{
+    if (b->table) return (KSlab *)(uintptr_t)b->table + s;
+    return &b->slab[s];
+}
+
 __device__ __forceinline__ void select_slab(KBatch *b, int s, BPSlab &out)
 {
-    out.sino = b->slab[s].sino;
-    out.image = b->slab[s].image;
-    out.cs = b->slab[s].cs;
-    out.csd = b->slab[s].csd;
-    out.center = b->slab[s].center;
-    out.item_begin = b->slab[s].item_begin;
-    out.n_angles = b->slab[s].n_angles;
-    out.n_det = b->slab[s].n_det;
-    out.nx = b->slab[s].nx;
-    out.ny = b->slab[s].ny;
-    out.n_slices = b->slab[s].n_slices;
-    out.tiles_x = b->slab[s].tiles_x;
-    out.tiles_y = b->slab[s].tiles_y;
-    out.mirror = b->slab[s].mirror;
-    out.scale = b->slab[s].scale;
-    out.accumulate = b->slab[s].accumulate;
-    out.out_u16 = b->slab[s].out_u16;
-    out.code_a = b->slab[s].code_a;
-    out.code_b = b->slab[s].code_b;
-    out.sets = b->slab[s].sets;
+    KSlab *d = slab_at(b, s);
+    out.sino = d->sino;
+    out.image = d->image;
+    out.cs = d->cs;
+    out.csd = d->csd;
+    out.center = d->center;
+    out.item_begin = d->item_begin;
+    out.n_angles = d->n_angles;
+    out.n_det = d->n_det;
+    out.nx = d->nx;
+    out.ny = d->ny;
+    out.n_slices = d->n_slices;
+    out.tiles_x = d->tiles_x;
+    out.tiles_y = d->tiles_y;
+    out.mirror = d->mirror;
+    out.scale = d->scale;
+    out.accumulate = d->accumulate;
+    out.out_u16 = d->out_u16;
+    out.code_a = d->code_a;
+    out.code_b = d->code_b;
+    out.sets = d->sets;
 }
 
 // Store of voxel `idx` (slab-wide index) from its accumulated sum: v = scale
@@ -115,13 +129,17 @@ __device__ __forceinline__ void store_voxel(const BPSlab &sl, int64_t idx, float
     }
 }
 
+// Slab of a work item: the last slab whose first item is at or before it
+// (binary search over the increasing item_begin; uniform, scalar loads).
 __device__ __forceinline__ int find_slab(KBatch *b, int64_t item)
 {
-    int s = 0;
-    const int n = b->n_slabs;
-    for (int i = 1; i < n; ++i)
-        if (item >= b->slab[i].item_begin) s = i;
-    return s;
+    int lo = 0, hi = b->n_slabs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (slab_at(b, mid)->item_begin <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
 }
 
 // The same value in every lane, as a scalar: everything derived from it
@@ -132,13 +150,35 @@ __device__ __forceinline__ int64_t uniform64(int64_t v)
            ((int64_t)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32);
 }
 
-// Next work item of this workgroup: the block index (optionally remapped so
-// that consecutive items share one XCD's L2), or a grab from the persistent
-// counter.  Returns a value >= total when the workgroup is done.
+// Next work item of this workgroup; a value >= total_items when it is done.
+//  * Non-persistent launch: one item per workgroup, item_base + the block
+//    index, optionally remapped so that XCD x (blocks x, x + 8, ...) takes the
+//    contiguous range [x n/8, (x+1) n/8) of the launch's n items.
+//  * Persistent launch: the items are dealt to the XCDs in bundles of
+//    kXcdBundle consecutive items (bundle i to XCD i mod 8), and each XCD
+//    walks its own bundles in order with its own counter, so the global order
+//    (most expensive slab first) is kept while one XCD's workgroups take
+//    neighbouring tiles.  A workgroup whose XCD has run out takes items from
+//    the other XCDs' counters in turn.  Which XCD a workgroup runs on only
+//    affects locality: every item is taken exactly once either way.
 __device__ __forceinline__ int64_t next_item(KBatch *b, int64_t *slot, int iter)
 {
     if (b->counter) {
-        if (threadIdx.x == 0) *slot = (int64_t)atomicAdd(b->counter, 1u);
+        if (threadIdx.x == 0) {
+            const int home = blockIdx.x % kXcds;
+            int64_t it = b->total_items;
+            for (int t = 0; t < kXcds; ++t) {
+                const int x = (home + t) % kXcds;
+                const unsigned c = atomicAdd(b->counter + x, 1u);
+                const int64_t bundle = (int64_t)(c / kXcdBundle) * kXcds + x;
+                const int64_t cand = bundle * kXcdBundle + c % kXcdBundle;
+                if (cand < b->total_items) {
+                    it = cand;
+                    break;
+                }
+            }
+            *slot = it;
+        }
         __syncthreads();
         const int64_t it = *slot;
         __syncthreads();
@@ -147,12 +187,10 @@ __device__ __forceinline__ int64_t next_item(KBatch *b, int64_t *slot, int iter)
     if (iter > 0) return b->total_items;
     int64_t bid = blockIdx.x;
     if (b->xcd_remap) {
-        // blocks are dispatched round-robin over the 8 XCDs; give XCD x the
-        // contiguous item range [x*n/8, (x+1)*n/8)
-        const int64_t per = b->total_items >> 3;
+        const int64_t per = gridDim.x >> 3;
         bid = (bid & 7) * per + (bid >> 3);
     }
-    return bid;
+    return b->item_base + bid;
 }
 
 // Pixel lattice of one thread inside a 64 x 64 tile: a wave covers an 8 x 8
@@ -561,6 +599,39 @@ __global__ __launch_bounds__(sym_threads<SL>(), sym_waves<SL>()) void bp_sym_ker
     }
 }
 
+// ---------------------------------------------------------------- slab table
+
+// Slab descriptors passed by value; the kernel copies them word by word from
+// its argument segment into the device table with vector stores.
+struct SlabChunk {
+    BPSlab s[kInlineSlabs];
+};
+static_assert(sizeof(BPSlab) % 4 == 0, "slab descriptors are copied as 32-bit words");
+
+__global__ __launch_bounds__(256) void write_slab_table_kernel(SlabChunk c, int n, BPSlab *dst)
+{
+    typedef const __attribute__((address_space(4))) uint32_t KWord;
+    KWord *src = (KWord *)__builtin_amdgcn_kernarg_segment_ptr();  // c sits at offset 0
+    uint32_t *d = reinterpret_cast<uint32_t *>(dst);
+    const int words = n * (int)(sizeof(BPSlab) / 4);
+    for (int i = threadIdx.x; i < words; i += blockDim.x) d[i] = src[i];
+}
+
+hipError_t write_slab_table(BPSlab *dst, const BPSlab *src, int n, hipStream_t s)
+{
+    (void)hipGetLastError();
+    for (int i = 0; i < n; i += kInlineSlabs) {
+        const int m = n - i < kInlineSlabs ? n - i : kInlineSlabs;
+        SlabChunk c;
+        std::memset(&c, 0, sizeof(c));
+        std::memcpy(c.s, src + i, sizeof(BPSlab) * (size_t)m);
+        hipLaunchKernelGGL(write_slab_table_kernel, dim3(1), dim3(256), 0, s, c, m, dst + i);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // ---------------------------------------------------------------- launchers
 
 // Opt in to more than 64 KiB of dynamic LDS only when a launch needs it.
@@ -625,6 +696,12 @@ hipError_t launch_bp(int path, const BPBatch &b, int dtype, int sl, int grid, si
 {
     return with_kernel(path, dtype, b.win, sl,
                        [&](auto k, int threads) { return launch(k, threads, b, grid, lds, s); });
+}
+
+int bp_block_threads(int path, int sl)
+{
+    if (path == kPathGeneric) return kBPThreads;
+    return sl == 2 ? sym_threads<2>() : sym_threads<1>();
 }
 
 int bp_max_blocks_per_cu(int path, int dtype, int win, int sl, size_t lds)

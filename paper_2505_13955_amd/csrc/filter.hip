@@ -346,7 +346,7 @@ __global__ __launch_bounds__(1024) void filter_kernel(FilterArgs a)
     extern __shared__ float2 z[];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int L = a.L, M = L >> 1, nc = a.nc;
-    const int64_t r = blockIdx.x;
+    const int64_t r = a.row_base + blockIdx.x;
 
     // Every global read of the workgroup is issued here, before the first
     // wait: the row's samples, the twiddle table, and the spectrum pass's
@@ -446,8 +446,17 @@ static hipError_t launch_typed(const FilterArgs &a, hipStream_t s)
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((filter_kernel<TI, TO, PRE>), dim3((unsigned)a.rows), dim3(nt), lds, s, a);
-    return hipGetLastError();
+    // one workgroup per row; a grid is at most 2^32 - 1 work-items
+    const int64_t max_rows = ((((int64_t)1 << 32) - 1) / nt);
+    FilterArgs c = a;
+    for (int64_t r0 = 0; r0 < a.rows; r0 += max_rows) {
+        c.row_base = r0;
+        const int64_t n = a.rows - r0 < max_rows ? a.rows - r0 : max_rows;
+        hipLaunchKernelGGL((filter_kernel<TI, TO, PRE>), dim3((unsigned)n), dim3(nt), lds, s, c);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <typename TI, bool PRE>

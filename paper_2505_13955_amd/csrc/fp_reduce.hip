@@ -63,8 +63,9 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
     __shared__ VT tile[kFPLdsFloats / SL];
     __shared__ int2 range;  // (first staged cross index, staged width)
     const int tid = threadIdx.x;
-    const int blk = blockIdx.x / a.bin_blocks;
-    const int bb = blockIdx.x - blk * a.bin_blocks;
+    const int wg = a.block_base + (int)blockIdx.x;
+    const int blk = wg / a.bin_blocks;
+    const int bb = wg - blk * a.bin_blocks;
     const int z0 = blockIdx.y * SL;
     const int nsl = min(SL, a.n_slices - z0);  // slices present in this group
     const FPBlock B = a.blocks[blk];
@@ -236,13 +237,23 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
 
 hipError_t launch_forward(const FPArgs &a, int sl, hipStream_t s)
 {
-    dim3 grid((unsigned)(a.n_blocks * a.bin_blocks), (unsigned)((a.n_slices + sl - 1) / sl));
+    // x: (angle block, bin block) pairs, split so that no launch exceeds
+    // 2^32 - 1 work-items along x; y: groups of `sl` slices
+    const int64_t total = (int64_t)a.n_blocks * a.bin_blocks;
+    const int64_t max_x = ((((int64_t)1 << 32) - 1) / kFPBins);
     (void)hipGetLastError();
-    if (sl == 4)
-        hipLaunchKernelGGL(fp_tile_kernel<4>, grid, dim3(kFPBins), 0, s, a);
-    else
-        hipLaunchKernelGGL(fp_tile_kernel<1>, grid, dim3(kFPBins), 0, s, a);
-    return hipGetLastError();
+    FPArgs c = a;
+    for (int64_t x0 = 0; x0 < total; x0 += max_x) {
+        c.block_base = (int32_t)x0;
+        dim3 grid((unsigned)(total - x0 < max_x ? total - x0 : max_x), (unsigned)((a.n_slices + sl - 1) / sl));
+        if (sl == 4)
+            hipLaunchKernelGGL(fp_tile_kernel<4>, grid, dim3(kFPBins), 0, s, c);
+        else
+            hipLaunchKernelGGL(fp_tile_kernel<1>, grid, dim3(kFPBins), 0, s, c);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // ---------------------------------------------------------------- forward projector plan

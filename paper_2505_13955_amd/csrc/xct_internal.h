@@ -10,7 +10,8 @@
 
 namespace xct {
 
-constexpr int kMaxSlabs = 16;
+constexpr int kInlineSlabs = 8;     // slabs a back-projection launch carries in its arguments
+constexpr int kMaxSlabs = 1 << 16;  // slabs of one xct_fbp_batch call
 constexpr int kTile = 64;          // back-projection tile edge (pixels)
 constexpr int kBPThreads = 256;    // back-projection workgroup size
 #ifndef XCT_SYM2_THREADS
@@ -44,15 +45,35 @@ struct BPSlab {
     int32_t sets;              // symmetric path: half-turn angle sets (2 for a full turn)
 };
 
+// Slabs, items and schedule of one back-projection launch.  Up to
+// kInlineSlabs slab descriptors travel in the kernel arguments; a launch over
+// more reads them from a device table (`table`, written on the launch's
+// stream by write_slab_table before the launch).
 struct BPBatch {
-    BPSlab slab[kMaxSlabs];
+    BPSlab slab[kInlineSlabs];
+    const BPSlab *table;    // device [n_slabs] descriptors, or nullptr (use `slab`)
     int64_t total_items;
-    unsigned int *counter;  // persistent work counter, or nullptr (one item per block)
+    int64_t item_base;      // first item of a non-persistent launch (grids are split
+                            // so that no launch exceeds 2^32 work-items)
+    unsigned int *counter;  // persistent work counters (kXcds of them), or nullptr
     int32_t n_slabs;
     int32_t win;            // window entries per angle and window
     int32_t kb;             // angles (generic) / angle pairs (symmetric) per LDS stage
     int32_t xcd_remap;      // map consecutive items to one XCD (non-persistent launches)
 };
+
+// Accelerator complex dies of an MI355X: workgroups are dispatched to them
+// round-robin, and each has its own L2.
+constexpr int kXcds = 8;
+// Items of a persistent launch are dealt to the XCDs in bundles of this many
+// consecutive items (one 4 x 4 group of neighbouring tiles), so the
+// workgroups of one XCD share detector windows in its L2.
+constexpr int kXcdBundle = 16;
+
+// Copy `n` slab descriptors (host array) into the device table `dst` with
+// kernels on stream s (the descriptors travel as kernel arguments, so the
+// copy is ordered on the stream and needs no host buffer to outlive the call).
+hipError_t write_slab_table(BPSlab *dst, const BPSlab *src, int n, hipStream_t s);
 
 // Back-projection kernels: any geometry, or quarter-turn + mirror symmetric.
 enum { kPathGeneric = 0, kPathSymmetric = 1 };
@@ -64,6 +85,7 @@ size_t bp_generic_lds_bytes(int win, int kb);
 size_t bp_sym_lds_bytes(int win, int kb, int sl);
 int bp_sym_window(int need);  // window of the symmetric kernel covering `need` (0: none)
 int bp_max_blocks_per_cu(int path, int dtype, int win, int sl, size_t lds);
+int bp_block_threads(int path, int sl);  // threads per workgroup of the kernel
 
 // Front end read in the filter's load phase: raw projection stack
 // [n_angles][n_rows][Nc] with dark and flat fields [n_rows][Nc].
@@ -84,6 +106,8 @@ struct FilterArgs {
     const float2 *tw;  // [L] exp(-2 pi i e / L)
     const float *H;    // [L] real spectrum / (L * pitch)
     int64_t rows;
+    int64_t row_base;  // row of workgroup 0 (grids are split so that no launch
+                       // exceeds 2^32 work-items)
     int32_t nc;
     int32_t L;
     int32_t log2L;
@@ -120,6 +144,7 @@ struct FPArgs {
     const FPAngle *ang;  // [Np]
     const FPBlock *blocks;
     int32_t n_blocks, bin_blocks;
+    int32_t block_base;  // (angle block, bin block) index of workgroup x = 0
     int32_t rows;        // walk steps staged at a time (power of two)
     int32_t pitch;       // LDS floats per staged walk step
     float scale;

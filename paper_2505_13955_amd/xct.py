@@ -15,9 +15,7 @@ det_pitch, pixel_size, center`` and a float64 ``angles`` array of length
 from __future__ import annotations
 
 import ctypes
-import math
 import os
-import types
 
 import numpy as np
 import torch
@@ -69,6 +67,7 @@ EXPORTS = (
     "xct_backproject",
     "xct_backproject_u16",
     "xct_forward_project",
+    "xct_project_adjoint",
     "xct_fbp_workspace_bytes",
     "xct_fbp_batch",
     "xct_reduce_workspace_bytes",
@@ -105,6 +104,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "xct_backproject_u16": ([gp, i32, vp, i32, vp, ctypes.c_float, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_double, vp], ctypes.c_int),
         "xct_forward_project": ([gp, i32, vp, vp, ctypes.c_float, i32, vp], ctypes.c_int),
+        "xct_project_adjoint": ([gp, i32, vp, vp, ctypes.c_float, i32, vp], ctypes.c_int),
         "xct_fbp_workspace_bytes": ([sp, i32, i32], sz),
         "xct_fbp_batch": ([sp, i32, i32, i32, i32, vp, sz, vp], ctypes.c_int),
         "xct_reduce_workspace_bytes": ([i64], sz),
@@ -206,19 +206,12 @@ def xct_filter_offset(geom, sino: torch.Tensor, filtered: torch.Tensor, window: 
 
 
 def fbp_offset(sino: torch.Tensor, geom, window: str, overlap: float,
-               filtered_dtype=torch.float32) -> torch.Tensor:
-    """Full-turn offset-scan FBP of sino (S, N_p, N_c): redundancy-weighted
-    filter on the virtual detector, then the back-projection through it with
-    weight 2 pi / N_p."""
-    nv, cv = xct_offset_detector(geom)
-    S = sino.shape[0]
-    q = torch.empty((S, geom.n_angles, nv), dtype=filtered_dtype, device=sino.device)
-    xct_filter_offset(geom, sino, q, window, overlap)
-    virt = types.SimpleNamespace(n_angles=geom.n_angles, n_det=nv, nx=geom.nx, ny=geom.ny,
-                                 det_pitch=geom.det_pitch, pixel_size=geom.pixel_size, center=cv,
-                                 angles=geom.angles)
-    img = torch.empty((S, geom.ny, geom.nx), dtype=torch.float32, device=sino.device)
-    xct_backproject(virt, q, img, 2.0 * math.pi / geom.n_angles, False)
+               filtered_dtype=torch.float32, workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Full-turn offset-scan FBP of sino (S, N_p, N_c) through xct_fbp_batch
+    (redundancy-weighted filter on the virtual detector, back-projection
+    through it; every constant is applied by the library)."""
+    img = torch.empty((sino.shape[0], geom.ny, geom.nx), dtype=torch.float32, device=sino.device)
+    xct_fbp_batch([(geom, sino, img, overlap)], window, filtered_dtype, workspace)
     return img
 
 
@@ -273,19 +266,30 @@ def xct_backproject_u16(geom, sino: torch.Tensor, image: torch.Tensor, scale: fl
     _check("xct_backproject_u16", rc)
 
 
-def xct_forward_project(geom, image: torch.Tensor, sino: torch.Tensor, scale: float | None = None,
+def xct_forward_project(geom, image: torch.Tensor, sino: torch.Tensor, alpha: float = 1.0,
                         accumulate: bool = False) -> None:
-    """sino = (accumulate ? sino : 0) + scale * A image; scale defaults to
-    pixel^2/pitch (the projector P)."""
+    """sino = (accumulate ? sino : 0) + alpha * P image, P = (pixel^2/pitch) A."""
     lib = load_library()
     S = _slices(image, geom, True)
     p_in = _dev(image, "image", (torch.float32,))
     p_out = _dev(sino, "sino", (torch.float32,), (S, geom.n_angles, geom.n_det))
     g, ang = make_geometry(geom)
-    sc = adjoint_scale(geom) if scale is None else float(scale)
-    rc = lib.xct_forward_project(ctypes.byref(g), S, p_in, p_out, sc, 1 if accumulate else 0,
+    rc = lib.xct_forward_project(ctypes.byref(g), S, p_in, p_out, float(alpha), 1 if accumulate else 0,
                                  _stream(image))
     _check("xct_forward_project", rc)
+
+
+def xct_project_adjoint(geom, sino: torch.Tensor, image: torch.Tensor, alpha: float = 1.0,
+                        accumulate: bool = False) -> None:
+    """image = (accumulate ? image : 0) + alpha * P^T sino (FP32 sinogram)."""
+    lib = load_library()
+    S = _slices(sino, geom, False)
+    p_in = _dev(sino, "sino", (torch.float32,))
+    p_out = _dev(image, "image", (torch.float32,), (S, geom.ny, geom.nx))
+    g, ang = make_geometry(geom)
+    rc = lib.xct_project_adjoint(ctypes.byref(g), S, p_in, p_out, float(alpha), 1 if accumulate else 0,
+                                 _stream(sino))
+    _check("xct_project_adjoint", rc)
 
 
 def _slab_array(slabs):
@@ -373,14 +377,6 @@ def xct_cache_clear() -> None:
 
 # ---------------------------------------------------------------- conveniences
 
-def fbp_weight(geom) -> float:
-    return math.pi / geom.n_angles
-
-
-def adjoint_scale(geom) -> float:
-    return geom.pixel_size ** 2 / geom.det_pitch
-
-
 def filter(sino: torch.Tensor, geom, window: str, out_dtype=torch.float32) -> torch.Tensor:
     out = torch.empty(sino.shape, dtype=out_dtype, device=sino.device)
     xct_filter(geom, sino, out, window)
@@ -388,19 +384,31 @@ def filter(sino: torch.Tensor, geom, window: str, out_dtype=torch.float32) -> to
 
 
 def backproject(sino: torch.Tensor, geom, scale: float = 1.0) -> torch.Tensor:
+    """scale * A^T sino (the plain back-projector; any storage dtype)."""
     img = torch.empty((sino.shape[0], geom.ny, geom.nx), dtype=torch.float32, device=sino.device)
     xct_backproject(geom, sino, img, scale, False)
     return img
 
 
 def forward_project(image: torch.Tensor, geom) -> torch.Tensor:
+    """P image for image (S, N_y, N_x)."""
     out = torch.empty((image.shape[0], geom.n_angles, geom.n_det), dtype=torch.float32,
                       device=image.device)
     xct_forward_project(geom, image, out)
     return out
 
 
-def fbp(sino: torch.Tensor, geom, window: str, filtered_dtype=torch.float32) -> torch.Tensor:
+def project_adjoint(sino: torch.Tensor, geom) -> torch.Tensor:
+    """P^T sino for an FP32 sinogram (S, N_p, N_c)."""
     img = torch.empty((sino.shape[0], geom.ny, geom.nx), dtype=torch.float32, device=sino.device)
-    xct_fbp_batch([(geom, sino, img)], window, filtered_dtype)
+    xct_project_adjoint(geom, sino, img)
+    return img
+
+
+def fbp(sino: torch.Tensor, geom, window: str, filtered_dtype=torch.float32,
+        workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Filtered back-projection of a half-turn scan (S, N_p, N_c) through
+    xct_fbp_batch."""
+    img = torch.empty((sino.shape[0], geom.ny, geom.nx), dtype=torch.float32, device=sino.device)
+    xct_fbp_batch([(geom, sino, img)], window, filtered_dtype, workspace)
     return img

@@ -17,6 +17,9 @@ Each spec mirrors one of the workloads the repository is measured on:
   per slice, Poisson noise at 1e4 photons.
 * ``c6``: offset scan, 8 slices of 4096^2, 8192 angles over a full turn, 4096
   bins with the axis at bin 1024, Hann, the aggregate / void phantom.
+* ``c7``: the paper-resolution slab with an odd angle count: 8192^2, 6143
+  angles over a half turn (a set not closed under quarter turns), 8192 bins,
+  Hann, the aggregate / void phantom.
 
 Every slice draws its phantom and noise from ``SeedSequence([config, slice])``,
 so any subset of slices can be regenerated on its own.  ``shrink`` builds a
@@ -149,6 +152,12 @@ def c6(n_slices: int = 8) -> SlabSpec:
     return SlabSpec("c6", 6, g, n_slices, "hann", "aggregate", 200, (), offset_overlap=1024.0)
 
 
+def c7(n_slices: int = 4) -> SlabSpec:
+    """8192^2 slices with 6143 angles over [0, pi): the same scan as c3 with an
+    angle count that no quarter turn maps onto itself."""
+    return SlabSpec("c7", 7, _geom(8192, 6143, 8192), n_slices, "hann", "aggregate", 200, ())
+
+
 def shrink(spec: SlabSpec, n: int, n_angles: int, n_slices: int) -> SlabSpec:
     """Same recipe at a smaller size: n^2 pixels, n_angles angles, detector
     width scaled with n (centre kept in the same relative place)."""
@@ -159,4 +168,4 @@ def shrink(spec: SlabSpec, n: int, n_angles: int, n_slices: int) -> SlabSpec:
     return dataclasses.replace(spec, geom=_geom(n, n_angles, n_det, center), n_slices=n_slices)
 
 
-ALL = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c6": c6}
+ALL = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c6": c6, "c7": c7}

@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_version_and_status_strings(lib):
-    assert lib.xct_version() == 10000
+    assert lib.xct_version() == 10100
     assert lib.xct_status_string(0) == b"ok"
     for code in (-1, -2, -3, -4, -5):
         assert lib.xct_status_string(code) not in (b"ok", b"unknown status")
@@ -68,6 +68,7 @@ def test_geometry_validation(lib, kw, code):
     g, ang = _geom(**kw)
     assert lib.xct_backproject(ctypes.byref(g), 1, FAKE, 0, FAKE, 1.0, 0, None) == code
     assert lib.xct_forward_project(ctypes.byref(g), 1, FAKE, FAKE, 1.0, 0, None) == code
+    assert lib.xct_project_adjoint(ctypes.byref(g), 1, FAKE, FAKE, 1.0, 0, None) == code
 
 
 def test_angle_validation(lib):
@@ -99,6 +100,10 @@ def test_backproject_validation(lib):
     assert lib.xct_backproject(None, 1, FAKE, 0, FAKE, 1.0, 0, None) == EINVAL
     assert lib.xct_forward_project(ctypes.byref(g), 70000, FAKE, FAKE, 1.0, 0, None) == ETOOBIG
     assert lib.xct_forward_project(ctypes.byref(g), 1, FAKE, FAKE, float("inf"), 0, None) == EINVAL
+    assert lib.xct_forward_project(ctypes.byref(g), 1, None, FAKE, 1.0, 0, None) == EINVAL
+    assert lib.xct_project_adjoint(ctypes.byref(g), 1, FAKE, FAKE, float("nan"), 0, None) == EINVAL
+    assert lib.xct_project_adjoint(ctypes.byref(g), 1, FAKE, None, 1.0, 0, None) == EINVAL
+    assert lib.xct_project_adjoint(ctypes.byref(g), 0, FAKE, FAKE, 1.0, 0, None) == EINVAL
 
 
 def test_preprocess_filter_validation(lib):
@@ -179,15 +184,18 @@ def test_fbp_batch_validation(lib):
         s.sino = FAKE
         s.image = FAKE
     need = lib.xct_fbp_workspace_bytes(slabs, 2, 0)
-    assert need == 256 + 2 * 1024  # two slabs of 2*8*16 FP32 values, 256-aligned
-    assert lib.xct_fbp_workspace_bytes(slabs, 2, 1) == 256 + 2 * 512
+    # counters (256 B), the slab table (two descriptors, 256-aligned), then two
+    # slabs of 2*8*16 FP32 values
+    assert need == 256 + 256 + 2 * 1024
+    assert lib.xct_fbp_workspace_bytes(slabs, 2, 1) == 256 + 256 + 2 * 512
     assert lib.xct_fbp_workspace_bytes(slabs, 0, 0) == 0
     ws = ctypes.c_void_p(0x10000)
     assert lib.xct_fbp_batch(slabs, 2, 0, 0, 0, ws, need - 1, None) == EWORKSPACE
     assert lib.xct_fbp_batch(slabs, 2, 0, 0, 0, ctypes.c_void_p(0x10010), need, None) == EWORKSPACE
     assert lib.xct_fbp_batch(slabs, 2, 0, 0, 0, None, need, None) == EWORKSPACE
     assert lib.xct_fbp_batch(slabs, 2, 0, 9, 0, ws, need, None) == EDTYPE
-    assert lib.xct_fbp_batch(slabs, 17, 0, 0, 0, ws, need, None) == ETOOBIG
+    assert lib.xct_fbp_batch(slabs, 65537, 0, 0, 0, ws, need, None) == ETOOBIG  # entries not read
+    assert lib.xct_fbp_workspace_bytes(slabs, 65537, 0) == 0
     slabs[1].image = None
     assert lib.xct_fbp_batch(slabs, 2, 0, 0, 0, ws, need, None) == EINVAL
 
@@ -212,3 +220,37 @@ def test_binding_rejects_host_tensors():
 
     with pytest.raises(ValueError):
         pkg.xct_backproject(G, torch.zeros(1, 8, 16), torch.zeros(1, 8, 8), 1.0)
+
+
+def test_fbp_workspace_grows_with_the_slab_table(lib):
+    """More slabs than one launch's arguments hold: the descriptor table takes
+    its own 256-byte-aligned region of the workspace, growing with the slab
+    count (no cap below 65536 slabs)."""
+    g, ang = _geom()
+    n = 40
+    slabs = (X.XctSlab * n)()
+    for s in slabs:
+        s.geom = g
+        s.n_slices = 1
+        s.sino = FAKE
+        s.image = FAKE
+    rows = 8 * 16 * 4  # one slice of filtered FP32 rows: 512 bytes, already aligned
+    table = [lib.xct_fbp_workspace_bytes(slabs, k, 0) - 256 - k * rows for k in range(1, n + 1)]
+    assert all(t > 0 and t % 256 == 0 for t in table)
+    assert all(b >= a for a, b in zip(table, table[1:])) and table[-1] > table[0]
+    assert table[-1] >= n * 64  # a descriptor holds at least its 8 pointers and sizes
+
+
+def test_no_device_reports_hip_error(lib):
+    """With no GPU present, a call that passes validation fails cleanly with
+    XCT_EHIP at its first HIP call (hipErrorNoDevice) and launches nothing."""
+    import torch
+
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present: this case needs a machine without one")
+    g, ang = _geom()
+    assert lib.xct_filter(ctypes.byref(g), 1, FAKE, 0, FAKE2, 0, 0, None) == -5
+    assert lib.xct_last_hip_error() != 0
+    assert lib.xct_backproject(ctypes.byref(g), 1, FAKE, 0, FAKE2, 1.0, 0, None) == -5
+    assert lib.xct_forward_project(ctypes.byref(g), 1, FAKE, FAKE2, 1.0, 0, None) == -5
+    assert lib.xct_dot_f64(FAKE, FAKE2, 10, FAKE, ctypes.c_void_p(0x10000), 8, None) == -5
