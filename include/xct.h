@@ -164,7 +164,11 @@ int xct_preprocess_filter(const xct_geometry *g, int32_t n_rows, int32_t row_beg
  *   image[s][i][j] = (accumulate ? image[s][i][j] : 0)
  *                    + scale * sum_k sum_n sino[s][k][n] K(u_k(x_j, y_i) - n)
  * Linear interpolation along the detector in FP32; FP16 / BF16 sinograms are
- * widened exactly and everything after is FP32.  FBP over a half turn uses
+ * widened exactly and everything after is FP32.  Kernel choice (results agree
+ * to FP32 rounding): square even slices with an angle set closed under
+ * quarter turns and 2c integral take the quarter-turn symmetric kernel; any
+ * other slice with 2c integral the mirror kernel (pixel pairs reflected
+ * through the slice centre, u -> 2c - u); the rest the generic kernel.  FBP over a half turn uses
  * scale = pi / N_p (xct_fbp_batch applies it itself). */
 int xct_backproject(const xct_geometry *g, int32_t n_slices, const void *sino, int32_t sino_t,
                     float *image, float scale, int32_t accumulate, xct_stream stream);
@@ -237,8 +241,9 @@ size_t xct_fbp_workspace_bytes(const xct_slab *slabs, int32_t n_slabs, int32_t f
  *   image = (pi / N_p) A^T ((1/det_pitch) h_W * sino)      per slice
  * The filter runs over every row of every slab into `workspace` (stored as
  * filtered_t), then ONE persistent back-projection launch per kernel variant
- * (the symmetric kernel for the slabs it serves, with two slices per work
- * item or, for single-slice slabs, one; the generic kernel for the rest)
+ * (the quarter-turn symmetric kernel, the mirror kernel and the generic
+ * kernel, the first two with two slices per work item or, for single-slice
+ * slabs, one)
  * walks all (slab, slice, tile) work items, most expensive slab first; the
  * work counters and the table of slab descriptors also live in the
  * workspace.  Every work item is computed whole by one workgroup with the

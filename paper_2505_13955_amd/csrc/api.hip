@@ -476,7 +476,18 @@ int symmetric_sets(const xct_geometry *g)
     return 0;
 }
 
-int choose_path(const xct_geometry *g) { return symmetric_sets(g) ? kPathSymmetric : kPathGeneric; }
+// Kernel path of a geometry: the quarter-turn + mirror symmetric kernel when
+// it applies; otherwise the mirror kernel when 2c is integral (detector bin
+// 2c - n exists for every bin n) and its windows fit; otherwise the generic
+// kernel.
+int choose_path(const xct_geometry *g)
+{
+    if (symmetric_sets(g)) return kPathSymmetric;
+    const double m = 2.0 * g->center;
+    if (std::fabs(m - std::nearbyint(m)) <= 1e-9 && bp_sym_window(window_entries(g->pixel_size / g->det_pitch)))
+        return kPathMirror;
+    return kPathGeneric;
+}
 
 struct BPJob {
     const xct_geometry *g;  // geometry the rows are back-projected with
@@ -499,6 +510,11 @@ int64_t plan_tiles(const BPJob &j, int sl, int *tx, int *ty)
         *tx = (j.g->nx + kTile - 1) / kTile;
         *ty = (j.g->ny + kTile - 1) / kTile;
         return (int64_t)*tx * *ty * j.n_slices;
+    }
+    if (j.path == kPathMirror) {  // the upper ceil(N_y/2) rows
+        *tx = (j.g->nx + kTile - 1) / kTile;
+        *ty = ((j.g->ny + 1) / 2 + kTile - 1) / kTile;
+        return (int64_t)*tx * *ty * ((j.n_slices + sl - 1) / sl);
     }
     const int q = (j.g->nx / 2 + kTile - 1) / kTile;  // tiles along a quadrant edge
     *tx = *ty = q;
@@ -532,7 +548,7 @@ int launch_bp_jobs(std::vector<BPJob> jobs, int dtype, unsigned int *counters, B
     std::stable_sort(jobs.begin(), jobs.end(),
                      [](const BPJob &a, const BPJob &b) { return a.g->n_angles > b.g->n_angles; });
     // two slices per work item when every slab has at least two
-    int spi = path == kPathSymmetric ? XCT_SYM_MAX_SLICES : 1;
+    int spi = path != kPathGeneric ? XCT_SYM_MAX_SLICES : 1;
     for (const BPJob &j : jobs)
         if (j.n_slices < 2) spi = 1;
     std::vector<BPSlab> desc(jobs.size());
@@ -558,7 +574,7 @@ int launch_bp_jobs(std::vector<BPJob> jobs, int dtype, unsigned int *counters, B
         sl.tiles_x = tx;
         sl.tiles_y = ty;
         sl.mirror = path != kPathGeneric ? (int32_t)std::nearbyint(2.0 * j.g->center) : 0;
-        sl.sets = path != kPathGeneric ? symmetric_sets(j.g) : 1;
+        sl.sets = path == kPathSymmetric ? symmetric_sets(j.g) : 1;
         sl.scale = j.scale;
         sl.accumulate = j.accumulate;
         sl.out_u16 = j.out_u16;
@@ -579,6 +595,11 @@ int launch_bp_jobs(std::vector<BPJob> jobs, int dtype, unsigned int *counters, B
         const size_t budget = spi == 2 ? kSym2StageBytes : kSymStageBytes;
         b.kb = (int)std::max<size_t>(1, budget / (4 * (size_t)W * spi * sizeof(float4) + 24));
         lds = bp_sym_lds_bytes(W, b.kb, spi);
+    } else if (path == kPathMirror) {
+        W = bp_sym_window(W);
+        const size_t budget = spi == 2 ? kSym2StageBytes : kSymStageBytes;
+        b.kb = (int)std::max<size_t>(1, budget / ((size_t)W * spi * sizeof(float4) + sizeof(float4)));
+        lds = bp_mirror_lds_bytes(W, b.kb, spi);
     } else {
         b.kb = (int)std::max<size_t>(1, std::min<size_t>(64, kGenericStageBytes / (8 * (size_t)W + 16)));
         lds = bp_generic_lds_bytes(W, b.kb);
@@ -913,7 +934,7 @@ size_t xct_fbp_workspace_bytes(const xct_slab *slabs, int32_t n_slabs, int32_t f
 int xct_fbp_batch(const xct_slab *slabs, int32_t n_slabs, int32_t sino_t, int32_t window,
                   int32_t filtered_t, void *workspace, size_t workspace_bytes, xct_stream stream)
 {
-    static_assert(3 * kXcds * sizeof(unsigned int) <= 256, "work counters exceed their region");
+    static_assert(5 * kXcds * sizeof(unsigned int) <= 256, "work counters exceed their region");
     if (int rc = check_slabs(slabs, n_slabs, true)) return rc;
     if (!dtype_ok(sino_t) || !dtype_ok(filtered_t)) return XCT_EDTYPE;
     if (window < XCT_RAM_LAK || window > XCT_HANN) return XCT_EDTYPE;
@@ -925,11 +946,11 @@ int xct_fbp_batch(const xct_slab *slabs, int32_t n_slabs, int32_t sino_t, int32_
     unsigned int *counters = reinterpret_cast<unsigned int *>(ws);
     BPSlab *table = reinterpret_cast<BPSlab *>(ws + 256);
     size_t off = 256 + table_bytes(n_slabs);
-    // Launch groups: the generic kernel; the symmetric kernel with one slice
-    // per item (single-slice slabs); the symmetric kernel with two slices per
-    // item.  A slab takes the kernel variant a call with that slab alone
-    // takes, so the images equal separate calls bit for bit.
-    enum { kGroupGeneric = 0, kGroupSym1 = 1, kGroupSym2 = 2, kGroups = 3 };
+    // Launch groups: the generic kernel; the mirror and the symmetric kernel,
+    // each with one slice per item (single-slice slabs) or two.  A slab takes
+    // the kernel variant a call with that slab alone takes, so the images
+    // equal separate calls bit for bit.
+    enum { kGroupGeneric = 0, kGroupMirror1, kGroupMirror2, kGroupSym1, kGroupSym2, kGroups };
     std::vector<BPJob> groups[kGroups];
     // back-projection geometry of offset slabs (virtual detector); lives until
     // the launches below have read it
@@ -963,7 +984,10 @@ int xct_fbp_batch(const xct_slab *slabs, int32_t n_slabs, int32_t sino_t, int32_
         j.accumulate = 0;
         j.path = choose_path(g);
         if (int rc = geo_tables(g, s, &j.t)) return rc;
-        const int grp = j.path == kPathGeneric ? kGroupGeneric : (j.n_slices >= 2 ? kGroupSym2 : kGroupSym1);
+        const int two = j.n_slices >= 2;
+        const int grp = j.path == kPathGeneric  ? kGroupGeneric
+                        : j.path == kPathMirror ? (two ? kGroupMirror2 : kGroupMirror1)
+                                                : (two ? kGroupSym2 : kGroupSym1);
         groups[grp].push_back(j);
     }
     hipError_t e = launch_fill_u32(counters, kGroups * kXcds, 0u, s);

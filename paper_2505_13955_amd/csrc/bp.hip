@@ -599,6 +599,178 @@ __global__ __launch_bounds__(sym_threads<SL>(), sym_waves<SL>()) void bp_sym_ker
     }
 }
 
+// ---------------------------------------------------------------- mirror
+
+// Point reflection through the slice centre: pixel Q = (i, j) and
+// R^2 Q = (N_y-1-i, N_x-1-j) have detector coordinates u and 2c - u at every
+// angle (the pixel grid is centred), so with 2c integral one coordinate and
+// one floor serve both, for any angle set and any slice shape.  A work item is
+// a 64 x 64 tile of the upper half of the slice (rows below ceil(N_y/2)) and
+// its reflection, all angles, SL slices.  Per angle the stage holds, for each
+// slice, one window of W 16-byte entries (a, d) forward and (a, d) mirrored,
+// indexed by the tile's local coordinate: one ds_read_b128 serves two
+// updates.  Middle-row pixels of an odd N_y reflect into the same row, where
+// they are their own tile's pixels: only Q is stored for them.
+size_t bp_mirror_lds_bytes(int win, int kb, int sl)
+{
+    return (size_t)kb * sizeof(float4) + (size_t)kb * win * sl * sizeof(float4);
+}
+
+template <typename T, int W, int SL>
+__global__ __launch_bounds__(sym_threads<SL>(), sym_waves<SL>()) void bp_mirror_kernel(BPBatch arg)
+{
+    KBatch *b = kernarg_batch();
+    extern __shared__ float4 lds4[];
+    __shared__ int64_t item_slot;
+    constexpr int kThreads = sym_threads<SL>();
+    constexpr int PX = 4096 / kThreads;  // pixels per thread
+    constexpr int ROWS = PX / 4;         // lattice rows per thread
+    constexpr int RS = kThreads / 16;    // lattice row stride
+    constexpr int PER = W * SL;          // float4 per angle
+    const int kb = b->kb;
+    float4 *par = lds4;                  // (u(tile centre) - B, C, S, B as int bits)
+    float4 *win = lds4 + kb;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int px = (lane & 7) | ((wv & 1) << 3);
+    const int py = (lane >> 3) | ((wv >> 1) << 3);
+    const float dxo = px - 31.5f, dyo = py - 31.5f;
+
+    for (int iter = 0;; ++iter) {
+        const int64_t item = uniform64(next_item(b, &item_slot, iter));
+        if (item >= b->total_items) break;
+        BPSlab sl;
+        select_slab(b, find_slab(b, item), sl);
+        const int64_t local = item - sl.item_begin;
+        const int tiles = sl.tiles_x * sl.tiles_y;
+        const int zg = __builtin_amdgcn_readfirstlane((int)(local / tiles));
+        const int t = __builtin_amdgcn_readfirstlane((int)(local - (int64_t)zg * tiles));
+        int ty, tx;
+        tile_position(t, sl.tiles_x, sl.tiles_y, ty, tx);
+        const int NX = sl.nx, NY = sl.ny, HY = (NY + 1) >> 1;
+        const int i0 = ty * kTile, j0 = tx * kTile;
+        const double xc = j0 + 31.5 - 0.5 * (NX - 1);
+        const double yc = i0 + 31.5 - 0.5 * (NY - 1);
+        const int Np = sl.n_angles, Nc = sl.n_det, M = sl.mirror;
+        const int z0 = zg * SL;
+        const int nsl = min(SL, sl.n_slices - z0);
+        const T *q = reinterpret_cast<const T *>(
+            uniform64(reinterpret_cast<int64_t>(static_cast<const T *>(sl.sino) + (int64_t)z0 * Np * Nc)));
+        const int64_t sl_stride = (int64_t)Np * Nc;
+
+        float acc[SL][2][PX];
+#pragma unroll
+        for (int s = 0; s < SL; ++s)
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int p = 0; p < PX; ++p) acc[s][r][p] = 0.0f;
+
+        for (int k0 = 0, nk = 0; k0 < Np; k0 += nk) {
+            nk = min(kb, Np - k0);
+            __syncthreads();
+            if (tid < nk) {
+                const double2 cd = sl.csd[k0 + tid];
+                const double E = 31.5 * (fabs(cd.x) + fabs(cd.y));
+                const double U = xc * cd.x + yc * cd.y + sl.center;
+                const double B = floor(U - E) - 1.0;
+                const float2 cf = sl.cs[k0 + tid];
+                par[tid] = make_float4((float)(U - B), cf.x, cf.y, __int_as_float((int)B));
+            }
+            __syncthreads();
+            // Staging units of 64 entries: (angle, slice, part), the angle's
+            // row a wave-uniform buffer resource (zero past the row's end,
+            // negative bins redirected there), loads of kU units in flight.
+            constexpr int kParts = (W + 63) / 64;
+            constexpr int kU = XCT_STAGE_UNITS;
+            constexpr int kWaves = kThreads / 64;
+            constexpr int D = SL * kParts;  // units per angle
+            const int wave = __builtin_amdgcn_readfirstlane(wv);
+            const int nunits = nk * D;
+            const T *qk = q + (int64_t)k0 * Nc;
+            for (int u0 = wave; u0 < nunits; u0 += kU * kWaves) {
+                float v[kU][4];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int unit = u0 + u * kWaves;
+                    const bool live = unit < nunits;
+                    const int kk = __builtin_amdgcn_readfirstlane(live ? unit / D : 0);
+                    const int rest = __builtin_amdgcn_readfirstlane(live ? unit - kk * D : 0);
+                    const int sidx = SL == 1 ? 0 : __builtin_amdgcn_readfirstlane(rest >= kParts);
+                    const int m = (rest - sidx * kParts) * 64 + lane;
+                    const int n = __float_as_int(par[kk].w) + m;
+                    const int rn = M - n;
+                    const T *row = reinterpret_cast<const T *>(uniform64(
+                        reinterpret_cast<int64_t>(qk + (sidx ? sl_stride : (int64_t)0) + (int64_t)kk * Nc)));
+                    const int len = __builtin_amdgcn_readfirstlane((live && sidx < nsl) ? Nc : 0);
+                    const auto rk = row_rsrc(row, len);
+                    v[u][0] = buf_elem<T>(rk, elem_offset<T>(n));
+                    v[u][1] = buf_elem<T>(rk, elem_offset<T>(n + 1));
+                    v[u][2] = buf_elem<T>(rk, elem_offset<T>(rn));
+                    v[u][3] = buf_elem<T>(rk, elem_offset<T>(rn - 1));
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int unit = u0 + u * kWaves;
+                    if (unit >= nunits) break;
+                    const int kk = unit / D, rest = unit - kk * D;
+                    const int sidx = SL == 1 ? 0 : (rest >= kParts);
+                    const int m = (rest - sidx * kParts) * 64 + lane;
+                    if (m < W) {
+                        const float f0 = v[u][0], fd = v[u][1] - f0, m0 = v[u][2], md = v[u][3] - m0;
+                        const float mf = -(float)m;
+                        win[kk * PER + sidx * W + m] = make_float4(fmaf(mf, fd, f0), fd, fmaf(mf, md, m0), md);
+                    }
+                }
+            }
+            __syncthreads();
+            for (int kk = 0; kk < nk; ++kk) {
+                const float4 p = par[kk];
+                const float C = p.y, S = p.z;
+                const float4 *wk = win + kk * PER;
+                const float c16 = 16.0f * C, sr = (float)RS * S;
+                float u_r = p.x + dxo * C + dyo * S;  // u(Q) - B
+#pragma unroll
+                for (int cc = 0; cc < ROWS; ++cc) {
+                    float u = u_r;
+#pragma unroll
+                    for (int aa = 0; aa < 4; ++aa) {
+                        const int n = (int)u;
+                        const int pi = cc * 4 + aa;
+#pragma unroll
+                        for (int s = 0; s < SL; ++s) {
+                            const float4 a = wk[s * W + n];
+                            acc[s][0][pi] += fmaf(u, a.y, a.x);   // Q
+                            acc[s][1][pi] += fmaf(u, a.w, a.z);   // R^2 Q
+                        }
+                        u += c16;
+                    }
+                    u_r += sr;
+                }
+            }
+        }
+
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+            if (s >= nsl) break;
+            const int64_t plane = (int64_t)(z0 + s) * NX * NY;
+#pragma unroll
+            for (int cc = 0; cc < ROWS; ++cc) {
+#pragma unroll
+                for (int aa = 0; aa < 4; ++aa) {
+                    const int i = i0 + py + RS * cc, j = j0 + px + 16 * aa;
+                    if (i < HY && j < NX) {
+                        const int pi = cc * 4 + aa;
+                        store_voxel(sl, plane + (int64_t)i * NX + j, acc[s][0][pi]);
+                        if (2 * i + 1 < NY)
+                            store_voxel(sl, plane + (int64_t)(NY - 1 - i) * NX + (NX - 1 - j), acc[s][1][pi]);
+                    }
+                }
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- slab table
 
 // Slab descriptors passed by value; the kernel copies them word by word from
@@ -681,6 +853,20 @@ static auto with_sym(int dtype, int win, F &&f)
     return f(bp_sym_kernel<bf16_t, 192, SL>, th);
 }
 
+template <int SL, typename F>
+static auto with_mirror(int dtype, int win, F &&f)
+{
+    constexpr int th = sym_threads<SL>();
+    if (win == 96) {
+        if (dtype == XCT_F32) return f(bp_mirror_kernel<float, 96, SL>, th);
+        if (dtype == XCT_F16) return f(bp_mirror_kernel<f16_t, 96, SL>, th);
+        return f(bp_mirror_kernel<bf16_t, 96, SL>, th);
+    }
+    if (dtype == XCT_F32) return f(bp_mirror_kernel<float, 192, SL>, th);
+    if (dtype == XCT_F16) return f(bp_mirror_kernel<f16_t, 192, SL>, th);
+    return f(bp_mirror_kernel<bf16_t, 192, SL>, th);
+}
+
 template <typename F>
 static auto with_kernel(int path, int dtype, int win, int sl, F &&f)
 {
@@ -689,6 +875,7 @@ static auto with_kernel(int path, int dtype, int win, int sl, F &&f)
         if (dtype == XCT_F16) return f(bp_generic_kernel<f16_t>, kBPThreads);
         return f(bp_generic_kernel<bf16_t>, kBPThreads);
     }
+    if (path == kPathMirror) return sl == 2 ? with_mirror<2>(dtype, win, f) : with_mirror<1>(dtype, win, f);
     return sl == 2 ? with_sym<2>(dtype, win, f) : with_sym<1>(dtype, win, f);
 }
 

@@ -75,14 +75,17 @@ constexpr int kXcdBundle = 16;
 // copy is ordered on the stream and needs no host buffer to outlive the call).
 hipError_t write_slab_table(BPSlab *dst, const BPSlab *src, int n, hipStream_t s);
 
-// Back-projection kernels: any geometry, or quarter-turn + mirror symmetric.
-enum { kPathGeneric = 0, kPathSymmetric = 1 };
+// Back-projection kernels: any geometry; quarter-turn + mirror symmetric
+// (square slices, angle sets closed under quarter turns, 2c integral); mirror
+// only (any slice and angle set, 2c integral).
+enum { kPathGeneric = 0, kPathSymmetric = 1, kPathMirror = 2 };
 
 // Launch (returns hipError_t of the launch) and sizing helpers.
 // `sl`: slices per work item of the symmetric kernel (1 or 2).
 hipError_t launch_bp(int path, const BPBatch &b, int dtype, int sl, int grid, size_t lds, hipStream_t s);
 size_t bp_generic_lds_bytes(int win, int kb);
 size_t bp_sym_lds_bytes(int win, int kb, int sl);
+size_t bp_mirror_lds_bytes(int win, int kb, int sl);
 int bp_sym_window(int need);  // window of the symmetric kernel covering `need` (0: none)
 int bp_max_blocks_per_cu(int path, int dtype, int win, int sl, size_t lds);
 int bp_block_threads(int path, int sl);  // threads per workgroup of the kernel

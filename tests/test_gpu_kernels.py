@@ -81,8 +81,10 @@ def test_filter_in_place(xct):
 
 # ---------------------------------------------------------------- back-projection
 BP_CASES = [
-    # (nx, ny, n_angles, n_det, pitch, pixel, center, angles) -> exercises the generic path
+    # (nx, ny, n_angles, n_det, pitch, pixel, center, angles)
+    # generic path: 2c not integral
     dict(nx=130, ny=70, n_angles=45, n_det=181, det_pitch=1.0, pixel_size=1.0, center=88.3, angles="rand"),
+    # mirror path: any angles and shape, 2c integral
     dict(nx=64, ny=64, n_angles=33, n_det=97, det_pitch=0.8, pixel_size=1.1, center=47.0, angles="rand"),
     dict(nx=1, ny=1, n_angles=3, n_det=5, det_pitch=1.0, pixel_size=1.0, center=2.0, angles="rand"),
     dict(nx=200, ny=3, n_angles=7, n_det=50, det_pitch=2.0, pixel_size=0.5, center=24.5, angles="rand"),
@@ -98,6 +100,14 @@ BP_CASES = [
     dict(nx=128, ny=128, n_angles=40, n_det=280, det_pitch=1.0, pixel_size=1.5, center=139.5, angles="uni"),
     # pixels 3 bins wide: generic kernel with wide windows
     dict(nx=60, ny=44, n_angles=21, n_det=260, det_pitch=0.5, pixel_size=1.5, center=129.5, angles="rand"),
+    # mirror path: odd width and height (a middle row that reflects onto
+    # itself), several tiles and ragged tails
+    dict(nx=151, ny=77, n_angles=61, n_det=181, det_pitch=1.0, pixel_size=1.0, center=90.0, angles="rand"),
+    dict(nx=64, ny=129, n_angles=50, n_det=160, det_pitch=1.0, pixel_size=1.0, center=79.5, angles="rand"),
+    # mirror path, uniform angles of odd count, pixels 1.5 bins wide (192-entry windows)
+    dict(nx=100, ny=100, n_angles=45, n_det=220, det_pitch=1.0, pixel_size=1.5, center=109.5, angles="uni"),
+    # mirror path, axis off the detector centre (mirrored bins partly off the detector)
+    dict(nx=90, ny=90, n_angles=37, n_det=140, det_pitch=1.0, pixel_size=1.0, center=80.0, angles="uni"),
 ]
 
 
@@ -138,9 +148,22 @@ def test_backproject_accumulate_and_scale(xct):
     assert rel_l2(img.cpu().numpy(), ref) < 2e-5
 
 
-def test_symmetric_and_generic_paths_agree(xct):
+@pytest.mark.parametrize("S", [1, 3])
+def test_mirror_path_slice_counts(xct, S):
+    """The mirror kernel with one slice per item (S = 1) and with a last
+    two-slice group holding one slice (S = 3), odd sizes."""
+    rng = np.random.default_rng(30 + S)
+    g = _geom(n_angles=29, n_det=150, nx=99, ny=71, center=74.5, angles=rng.uniform(0, math.pi, 29))
+    q = rng.standard_normal((S, 29, 150))
+    img = xct.backproject(to_dev(q), g, scale=1.3)
+    torch.cuda.synchronize()
+    ref = oracle.backproject(q.astype(np.float32).astype(np.float64), g, 1.3)
+    assert rel_l2(img.cpu().numpy(), ref) < 2e-5
+
+
+def test_symmetric_and_mirror_paths_agree(xct):
     """The same uniform geometry through the symmetric path, and through the
-    generic path (angles nudged so the quarter-turn pairing no longer holds)."""
+    mirror path (angles nudged so the quarter-turn pairing no longer holds)."""
     rng = np.random.default_rng(10)
     g = _geom(n_angles=90, n_det=181, nx=128, ny=128)
     ang = g.angles.copy()
@@ -274,9 +297,9 @@ def test_fbp_offset_matches_oracle(xct, case):
     assert rel_l2(img.cpu().numpy(), ref) < 2e-5
 
 
-def test_full_turn_symmetric_and_generic_paths_agree(xct):
+def test_full_turn_symmetric_and_mirror_paths_agree(xct):
     """A full-turn angle set (two half-turn sets) through the symmetric kernel,
-    and through the generic one (one angle nudged)."""
+    and through the mirror one (one angle nudged)."""
     rng = np.random.default_rng(19)
     g = _offset_geom(128, 160, 200, 99.5, 1.0)
     ang = g.angles.copy()
