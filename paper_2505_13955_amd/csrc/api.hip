@@ -431,20 +431,6 @@ int filter_tables(int nc, int window, double pitch, hipStream_t stream, EntryRef
     return cache_insert(key, parts, sizes, stream, meta, out);
 }
 
-int device_cus()
-{
-    static int cus[64] = {0};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-    if (!cus[dev]) {
-        int n = 0;
-        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
-            n = 256;
-        cus[dev] = n;
-    }
-    return cus[dev];
-}
-
 // ---------------------------------------------------------------- back-projection plan
 
 // Window entries per angle for a 64-pixel tile: the detector footprint of the
@@ -1035,3 +1021,18 @@ int xct_sqdist_f64(const float *a, const float *b, int64_t n, double *result, vo
 }
 
 }  // extern "C"
+
+// Compute units of the current device (cached per device).
+int xct::device_cus()
+{
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cus[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+        cus[dev] = n;
+    }
+    return cus[dev];
+}

@@ -19,12 +19,18 @@
 // 1/pitch fold into H / (L pitch).  The inverse is done as the conjugate of
 // the forward transform of conj Z'.
 //
-// The transform lives in LDS (M <= 8192 complex FP32 = 64 KiB, plus 8 KiB of
-// twiddles, so two workgroups share a CU) and runs as mixed-radix Stockham passes (radix 4,
-// plus one radix-2 pass when log2 M is odd); each pass reads its operands
-// into registers, synchronises, and writes the results in place.  Twiddles
-// come from a table of exp(-2 pi i e / L) computed on the host in FP64; the
-// passes read an eighth-turn copy of it held in LDS (M/8 + 1 entries).
+// Two kernels share this scheme.  Rows with M = L/2 >= 256 (N_c > 128, every
+// workload of the paper's sizes) take filter_fused_kernel: three Stockham
+// passes with 32 values per thread in registers, the spectrum step fused
+// between the last forward pass and its adjoint (four LDS exchanges per row);
+// it is described where it is defined.  Shorter rows take
+// filter_small_kernel: the transform lives in LDS as mixed-radix Stockham
+// passes (a radix-2 or radix-4 lead pass, then radix-16 passes), one LDS pass
+// for the spectrum step, and the inverse as the conjugate of the forward
+// transform of conj Z'; twiddles come from an eighth-turn copy of the
+// exp(-2 pi i e / L) table held in LDS.
+#include <type_traits>
+
 #include "xct_internal.h"
 
 namespace xct {
@@ -341,7 +347,7 @@ constexpr int kSpecRounds = 9;
 constexpr int kLoadRounds = 16;
 
 template <typename TI, typename TO, bool PRE>
-__global__ __launch_bounds__(1024) void filter_kernel(FilterArgs a)
+__global__ __launch_bounds__(1024) void filter_small_kernel(FilterArgs a)
 {
     extern __shared__ float2 z[];
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -432,6 +438,631 @@ __global__ __launch_bounds__(1024) void filter_kernel(FilterArgs a)
     }
 }
 
+// ============================================================== rows of 512 to 16384 points
+//
+// For M = L/2 >= 256 the transform runs as three Stockham passes with every
+// thread holding 32 complex values in registers (M/32 threads per row,
+// 256-thread workgroups of 8192/M rows, 64 KiB of LDS):
+//   P1: radix R1 (32 when log2 M is odd, else 16), span 1, straight from the
+//       input row (no exchange before it, no twiddles);
+//   P2: radix R2 = M/(16 R1) (4 or 16; none when M <= 512), span R1;
+//   P3: radix 16, span Ns = M/16.
+// The inverse is the adjoint of the forward passes run backwards (P3^H, P2^H,
+// P1^H; F^H = M IFFT), and P3^H reads the positions P3 writes, so P3, the
+// spectrum step and P3^H run in registers: each thread holds a butterfly j
+// of P3 and its mirror Ns - j, whose outputs at k = j + s Ns and
+// M - k = (Ns - j) + (15 - s) Ns pair up as the spectrum step needs (thread
+// 0 holds the two self-mirrored butterflies 0 and Ns/2).  P1^H writes the
+// output row.  Four LDS exchanges per row instead of ten.
+//
+// LDS index of position p: p with bits 0-4 XORed with a GF(2)-linear function
+// of bits 5-12 (columns kSwz), chosen so that the 32 lanes of every 8-byte
+// access of every exchange meet 32 distinct bank pairs, except the mirror
+// butterflies' accesses of P3, whose 32 lanes straddle two aligned groups
+// (two-way conflicts on half of that exchange's accesses).  Because the map
+// is linear and every position a thread touches is a per-thread part ORed
+// with a compile-time part, an access costs one XOR with a constant plus an
+// immediate offset.
+
+constexpr int kSwz[8] = {9, 19, 24, 20, 28, 6, 23, 1};
+
+__host__ __device__ constexpr int swz_hi(int q)
+{
+    int x = 0;
+    for (int b = 0; b < 8; ++b)
+        if ((q >> b) & 1) x ^= kSwz[b];
+    return x;
+}
+
+// LDS index of position p (p < 8192): linear over XOR.
+__host__ __device__ constexpr int lpos(int p) { return p ^ swz_hi(p >> 5); }
+
+// Element at position base | c, with sb = 8 lpos(base) (a byte offset) and c
+// a compile-time position whose bits are disjoint from base's: one XOR with
+// a constant, and the rest of c as the instruction's immediate offset.
+__device__ __forceinline__ float2 &lds_at(float2 *z, int sb, int c)
+{
+    const int x = (lpos(c) & 31) << 3;
+    return *reinterpret_cast<float2 *>(reinterpret_cast<char *>(z) + ((sb ^ x) + ((c & ~31) << 3)));
+}
+
+// The same value, recomputed rather than held: keeps the compiler from
+// carrying a pass's addresses or twiddles in registers to its adjoint.
+__device__ __forceinline__ int opaque_i(int v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cconj_mul(float2 a, float2 b)  // a conj(b)
+{
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+
+// multiply by -i (forward) or +i (adjoint)
+template <bool INV>
+__device__ __forceinline__ float2 rot_i(float2 x)
+{
+    return INV ? make_float2(-x.y, x.x) : make_float2(x.y, -x.x);
+}
+
+// cos and sin of 2 pi e / 64, e = 0 .. 63 (quarter turns exact)
+constexpr float kCos64[64] = {1.0f, 0.9951847195625305f, 0.9807852506637573f, 0.9569403529167175f, 0.9238795042037964f, 0.8819212913513184f, 0.8314695954322815f, 0.7730104327201843f, 0.7071067690849304f, 0.6343932747840881f, 0.5555702447891235f, 0.4713967442512512f, 0.3826834261417389f, 0.290284663438797f, 0.19509032368659973f, 0.0980171412229538f, 0.0f, -0.0980171412229538f, -0.19509032368659973f, -0.290284663438797f, -0.3826834261417389f, -0.4713967442512512f, -0.5555702447891235f, -0.6343932747840881f, -0.7071067690849304f, -0.7730104327201843f, -0.8314695954322815f, -0.8819212913513184f, -0.9238795042037964f, -0.9569403529167175f, -0.9807852506637573f, -0.9951847195625305f, -1.0f, -0.9951847195625305f, -0.9807852506637573f, -0.9569403529167175f, -0.9238795042037964f, -0.8819212913513184f, -0.8314695954322815f, -0.7730104327201843f, -0.7071067690849304f, -0.6343932747840881f, -0.5555702447891235f, -0.4713967442512512f, -0.3826834261417389f, -0.290284663438797f, -0.19509032368659973f, -0.0980171412229538f, 0.0f, 0.0980171412229538f, 0.19509032368659973f, 0.290284663438797f, 0.3826834261417389f, 0.4713967442512512f, 0.5555702447891235f, 0.6343932747840881f, 0.7071067690849304f, 0.7730104327201843f, 0.8314695954322815f, 0.8819212913513184f, 0.9238795042037964f, 0.9569403529167175f, 0.9807852506637573f, 0.9951847195625305f};
+constexpr float kSin64[64] = {0.0f, 0.0980171412229538f, 0.19509032368659973f, 0.290284663438797f, 0.3826834261417389f, 0.4713967442512512f, 0.5555702447891235f, 0.6343932747840881f, 0.7071067690849304f, 0.7730104327201843f, 0.8314695954322815f, 0.8819212913513184f, 0.9238795042037964f, 0.9569403529167175f, 0.9807852506637573f, 0.9951847195625305f, 1.0f, 0.9951847195625305f, 0.9807852506637573f, 0.9569403529167175f, 0.9238795042037964f, 0.8819212913513184f, 0.8314695954322815f, 0.7730104327201843f, 0.7071067690849304f, 0.6343932747840881f, 0.5555702447891235f, 0.4713967442512512f, 0.3826834261417389f, 0.290284663438797f, 0.19509032368659973f, 0.0980171412229538f, 0.0f, -0.0980171412229538f, -0.19509032368659973f, -0.290284663438797f, -0.3826834261417389f, -0.4713967442512512f, -0.5555702447891235f, -0.6343932747840881f, -0.7071067690849304f, -0.7730104327201843f, -0.8314695954322815f, -0.8819212913513184f, -0.9238795042037964f, -0.9569403529167175f, -0.9807852506637573f, -0.9951847195625305f, -1.0f, -0.9951847195625305f, -0.9807852506637573f, -0.9569403529167175f, -0.9238795042037964f, -0.8819212913513184f, -0.8314695954322815f, -0.7730104327201843f, -0.7071067690849304f, -0.6343932747840881f, -0.5555702447891235f, -0.4713967442512512f, -0.3826834261417389f, -0.290284663438797f, -0.19509032368659973f, -0.0980171412229538f};
+
+// exp(-2 pi i e / n) (forward) or its conjugate, n dividing 64
+template <bool INV>
+__device__ __forceinline__ float2 root(int e, int n)
+{
+    const int i = (((e % n) + n) % n) * (64 / n);
+    return make_float2(kCos64[i], INV ? kSin64[i] : -kSin64[i]);
+}
+
+template <bool INV>
+__device__ __forceinline__ void bfly4(float2 &x0, float2 &x1, float2 &x2, float2 &x3)
+{
+    const float2 a0 = cadd(x0, x2), a1 = csub(x0, x2), a2 = cadd(x1, x3), a3 = rot_i<INV>(csub(x1, x3));
+    x0 = cadd(a0, a2);
+    x1 = cadd(a1, a3);
+    x2 = csub(a0, a2);
+    x3 = csub(a1, a3);
+}
+
+// Multiply by the compile-time root exp(-+2 pi i e / n), with the trivial
+// quarter turns and the eighth turns done without a full product.
+template <bool INV>
+__device__ __forceinline__ float2 turn(float2 x, int e, int n)
+{
+    e %= n;
+    if (e == 0) return x;
+    if (4 * e == n) return rot_i<INV>(x);
+    if (2 * e == n) return make_float2(-x.x, -x.y);
+    if (4 * e == 3 * n) return rot_i<!INV>(x);
+    const float2 w = root<INV>(e, n);
+    return make_float2(x.x * w.x - x.y * w.y, x.x * w.y + x.y * w.x);
+}
+
+// DFT of 4, 16 or 32 points in registers (forward: exp(-2 pi i t s / R);
+// adjoint: the conjugate).  Input t in x[t]; output s in x[dft_slot<R>(s)].
+template <int R>
+__host__ __device__ constexpr int dft_slot(int s)
+{
+    return R == 4 ? s : R == 16 ? 4 * (s & 3) + (s >> 2) : ((s & 1) ? 16 : 0) + 4 * ((s >> 1) & 3) + (s >> 3);
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2 *x)
+{
+    if constexpr (R == 4) {
+        bfly4<INV>(x[0], x[1], x[2], x[3]);
+    } else if constexpr (R == 16) {
+        // t = 4 t1 + t2: DFT over t1 per t2, factors w16^(t2 s1), DFT over t2 per s1
+#pragma unroll
+        for (int t2 = 0; t2 < 4; ++t2) bfly4<INV>(x[t2], x[4 + t2], x[8 + t2], x[12 + t2]);
+#pragma unroll
+        for (int s1 = 1; s1 < 4; ++s1)
+#pragma unroll
+            for (int t2 = 1; t2 < 4; ++t2) x[4 * s1 + t2] = turn<INV>(x[4 * s1 + t2], s1 * t2, 16);
+#pragma unroll
+        for (int s1 = 0; s1 < 4; ++s1) bfly4<INV>(x[4 * s1], x[4 * s1 + 1], x[4 * s1 + 2], x[4 * s1 + 3]);
+    } else {
+        // t = b + 16 a: pairs (b, b + 16), factors w32^(b s1), 16-point DFTs over b
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+            const float2 u = x[b], v = x[b + 16];
+            x[b] = cadd(u, v);
+            x[b + 16] = turn<INV>(csub(u, v), b, 32);
+        }
+        dft<16, INV>(x);
+        dft<16, INV>(x + 16);
+    }
+}
+
+// Powers w^1 .. w^15 of a butterfly's twiddle from w and w^4 (at most three
+// products each); p[0] = 1.
+__device__ __forceinline__ void powers16(float2 w1, float2 w4, float2 *p)
+{
+    const float2 one = make_float2(1.0f, 0.0f);
+    const float2 w2 = cmul(w1, w1), w3 = cmul(w2, w1);
+    const float2 w8 = cmul(w4, w4), w12 = cmul(w8, w4);
+    const float2 base[4] = {one, w4, w8, w12}, fine[4] = {one, w1, w2, w3};
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) p[4 * a + b] = (a == 0) ? fine[b] : (b == 0) ? base[a] : cmul(base[a], fine[b]);
+}
+
+// Spectrum step for the bin pair (k, M - k) of the packed transform Z:
+// real-row spectrum X[k] = E + W^k O, X[M-k] = conj(E - W^k O) with
+// E = (Z[k] + conj Z[M-k]) / 2, O = (Z[k] - conj Z[M-k]) / 2i, times the
+// filter (hk = H[k], hm = H[M-k], scaled by 1 / (L pitch)), repacked as
+//   Z'[k]   = P + i Q,  P = Y[k] + conj Y[M-k],  Q = (Y[k] - conj Y[M-k]) W^-k
+//   Z'[M-k] = conj P + i conj Q,
+// whose adjoint transform F^H Z' is the filtered row (even samples in the
+// real parts, odd in the imaginary parts).  w = W^k = exp(-2 pi i k / L).
+__device__ __forceinline__ void spectrum_pair(float2 zk, float2 zm, float2 w, float hk, float hm, float2 &ok,
+                                              float2 &om)
+{
+    const float2 E = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+    const float2 O = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
+    const float2 WO = cmul(w, O);
+    const float2 Yk = make_float2(hk * (E.x + WO.x), hk * (E.y + WO.y));
+    const float2 Ym = make_float2(hm * (E.x - WO.x), -hm * (E.y - WO.y));
+    const float2 P = make_float2(Yk.x + Ym.x, Yk.y - Ym.y);
+    const float2 Q = cconj_mul(make_float2(Yk.x - Ym.x, Yk.y + Ym.y), w);
+    ok = make_float2(P.x - Q.y, P.y + Q.x);
+    om = make_float2(P.x + Q.y, Q.x - P.y);
+}
+
+// Keep the compiler from merging a recomputation with an earlier value (the
+// adjoint passes recompute their twiddle powers instead of holding them).
+__device__ __forceinline__ float2 opaque(float2 v)
+{
+    asm volatile("" : "+v"(v.x), "+v"(v.y));
+    return v;
+}
+
+// P1 inputs of the filter: element e = T + b TN + t M/R1 of row r holds
+// output bins 2e and 2e + 1; the input row's samples land on bins in_first ..
+// in_first + in_len - 1 (times `weight` when given), zero elsewhere.  Every
+// load reads a valid address (clamped) and the value is selected after, so
+// the loads issue back to back without branches.
+template <typename TI, bool SHIFTED>
+__device__ __forceinline__ float in_bin(const TI *p, const float *weight, int first, int len, int b)
+{
+    const int m = SHIFTED ? b - first : b;
+    const bool in = (unsigned)m < (unsigned)len;
+    const int mc = in ? m : 0;
+    float v = ld_in(p, mc);
+    if (SHIFTED && weight) v *= weight[mc];
+    return in ? v : 0.0f;
+}
+
+// Both samples of element e in one load (an unshifted row of even length
+// from a buffer aligned to two samples: every element is so aligned).
+template <typename TI>
+__device__ __forceinline__ float2 ld_pair(const TI *p, int e);
+template <>
+__device__ __forceinline__ float2 ld_pair<float>(const float *p, int e)
+{
+    return reinterpret_cast<const float2 *>(p)[e];
+}
+template <>
+__device__ __forceinline__ float2 ld_pair<f16_t>(const f16_t *p, int e)
+{
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    const h2 v = reinterpret_cast<const h2 *>(p)[e];
+    return make_float2((float)v.x, (float)v.y);
+}
+template <>
+__device__ __forceinline__ float2 ld_pair<bf16_t>(const bf16_t *p, int e)
+{
+    const uint32_t u = reinterpret_cast<const uint32_t *>(p)[e];
+    return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u));
+}
+
+// MODE 0: unshifted row of even length (pair loads); 1: unshifted; 2:
+// shifted and/or weighted.  The row fills at most the first half of the
+// packed elements (2e < in_first + in_len <= N_c <= M), so only inputs t <
+// R1/2 of each P1 butterfly are read: x[b * (R1/2) + t].
+template <int R1, int NB1, int TN, int M, typename TI, int MODE>
+__device__ __forceinline__ void load_p1(float2 *x, const FilterArgs &a, int64_t r, int T)
+{
+    const TI *p = static_cast<const TI *>(a.in) + r * a.in_len;
+    const float *w = a.weight;
+    const int first = a.in_first, len = a.in_len;
+#pragma unroll
+    for (int b = 0; b < NB1; ++b)
+#pragma unroll
+        for (int t = 0; t < R1 / 2; ++t) {
+            const int e = T + b * TN + t * (M / R1);
+            if constexpr (MODE == 0) {
+                const bool in = 2 * e < len;
+                const float2 v = ld_pair(p, in ? e : 0);
+                x[b * (R1 / 2) + t] = in ? v : make_float2(0.0f, 0.0f);
+            } else {
+                x[b * (R1 / 2) + t] = make_float2(in_bin<TI, MODE == 2>(p, w, first, len, 2 * e),
+                                                  in_bin<TI, MODE == 2>(p, w, first, len, 2 * e + 1));
+            }
+        }
+}
+
+template <int R1, int NB1, int TN, int M, typename TI>
+__device__ __forceinline__ void load_p1_t(float2 *x, const FilterArgs &a, int64_t r, int T)
+{
+    if (a.weight || a.in_first != 0) load_p1<R1, NB1, TN, M, TI, 2>(x, a, r, T);
+    else if ((a.in_len & 1) == 0 && reinterpret_cast<uintptr_t>(a.in) % (2 * sizeof(TI)) == 0)
+        load_p1<R1, NB1, TN, M, TI, 0>(x, a, r, T);
+    else load_p1<R1, NB1, TN, M, TI, 1>(x, a, r, T);
+}
+
+template <int R1, int NB1, int TN, int M>
+__device__ __forceinline__ void load_p1_any(float2 *x, const FilterArgs &a, int in_t, int64_t r, int T)
+{
+    if (in_t == XCT_F32) load_p1_t<R1, NB1, TN, M, float>(x, a, r, T);
+    else if (in_t == XCT_F16) load_p1_t<R1, NB1, TN, M, f16_t>(x, a, r, T);
+    else load_p1_t<R1, NB1, TN, M, bf16_t>(x, a, r, T);
+}
+
+// P1^H outputs: element e of the row holds bins 2e (real part) and 2e + 1;
+// only outputs t < R1/2 of each butterfly fall on the row (2e < N_c <= M).
+// An FP32 row of even length in an 8-byte aligned buffer takes both samples
+// in one 8-byte store.
+template <int R1, int NB1, int TN, int M, typename TO>
+__device__ __forceinline__ void store_p1(const float2 *x, const FilterArgs &a, int64_t r, int T)
+{
+    TO *o = static_cast<TO *>(a.out) + r * a.nc;
+    const int nc = a.nc;
+    const bool pairs = sizeof(TO) == 4 && (nc & 1) == 0 && reinterpret_cast<uintptr_t>(a.out) % 8 == 0;
+#pragma unroll
+    for (int b = 0; b < NB1; ++b)
+#pragma unroll
+        for (int t = 0; t < R1 / 2; ++t) {
+            const int e = T + b * TN + t * (M / R1);
+            const float2 v = x[b * R1 + dft_slot<R1>(t)];
+            if (pairs) {
+                if (2 * e < nc) reinterpret_cast<float2 *>(o)[e] = v;
+            } else {
+                if (2 * e < nc) st_out(o, 2 * e, v.x);
+                if (2 * e + 1 < nc) st_out(o, 2 * e + 1, v.y);
+            }
+        }
+}
+
+// Kernel kinds: the front end (raw projection stack); any row form with one
+// workgroup per group of rows; and persistent kernels for unshifted,
+// unweighted rows of even length in FP32, FP16 or BF16 that keep the next
+// group's samples in flight.
+enum { kFrontEnd = 0, kRows = 1, kPersistF32 = 2, kPersistF16 = 3, kPersistBF16 = 4 };
+
+template <int LOG2M, int KIND>
+__global__ __launch_bounds__(256) void filter_fused_kernel(FilterArgs a, int in_t, int out_t)
+{
+    constexpr bool PRE = KIND == kFrontEnd;
+    constexpr bool PERSIST = KIND >= kPersistF32;
+    typedef typename std::conditional<KIND == kPersistF16, f16_t,
+                                      typename std::conditional<KIND == kPersistBF16, bf16_t, float>::type>::type TP;
+    constexpr int M = 1 << LOG2M;
+    constexpr int R1 = (LOG2M & 1) ? 32 : 16;
+    constexpr int H1 = R1 / 2;         // P1 inputs per butterfly that can be non-zero
+    constexpr int R2 = (M / 16) / R1;  // 1 (no middle pass), 4 or 16
+    constexpr int NB1 = 32 / R1;       // P1 butterflies per thread
+    constexpr int NB2 = 32 / R2;       // P2 butterflies per thread
+    constexpr int NS = M / 16;         // span of P3
+    constexpr int TN = M / 32;         // threads per row
+    constexpr int ROWS = 256 / TN;     // rows per workgroup
+    static_assert(LOG2M >= 8 && LOG2M <= 13, "fused filter: 256 <= M <= 8192");
+    __shared__ float2 z[8192];
+
+    const int tid = threadIdx.x;
+    const int rho = tid / TN, T_h = tid % TN;
+    const int nc = a.nc;
+    const int rb = rho * M;  // the row's positions in LDS
+    // groups of ROWS rows; this workgroup takes groups blockIdx.x,
+    // blockIdx.x + gridDim.x, ...
+    const int64_t groups = (a.rows + ROWS - 1) / ROWS;
+
+    // Row-independent twiddles, read once: butterfly A = T of the last pass,
+    // its mirror B, and the middle pass's.
+    const int A_h = T_h;
+    const int B_h = T_h == 0 ? NS / 2 : NS - T_h;
+    const float2 WT_h = a.tw[T_h];                            // W^T, W = exp(-2 pi i / L)
+    const float2 w1A_h = a.tw[2 * A_h], w4A_h = a.tw[8 * A_h];  // exp(-2 pi i j / M), its fourth power
+    const float2 w1B_h = a.tw[2 * B_h], w4B_h = a.tw[8 * B_h];
+    float2 w21_h = make_float2(1.0f, 0.0f), w24_h = w21_h;  // exp(-2 pi i (T mod R1) / (R1 R2)), fourth power
+    if constexpr (R2 > 1) {
+        w21_h = a.tw[32 * (T_h & (R1 - 1))];
+        if constexpr (R2 == 16) w24_h = a.tw[128 * (T_h & (R1 - 1))];
+    }
+
+    // The plain filter holds the next group's P1 inputs in xn while the
+    // current group is transformed.
+    float2 xn[NB1 * H1];
+    int64_t g = blockIdx.x;
+    if constexpr (PERSIST) {
+        const int64_t r = g * ROWS + rho;
+        if (g < groups && r < a.rows) load_p1<R1, NB1, TN, M, TP, 0>(xn, a, r, T_h);
+        else
+#pragma unroll
+            for (int i = 0; i < NB1 * H1; ++i) xn[i] = make_float2(0.0f, 0.0f);
+    }
+
+    auto group = [&](int64_t g) {
+        // Values that do not change from group to group pass through opaque
+        // copies, so that what is derived from them (addresses, predicates,
+        // twiddle powers) is recomputed per group rather than held in
+        // registers across the loop.
+        const int T = opaque_i(T_h);
+        const int A = T;
+        const int B = opaque_i(B_h);
+        const float2 WT = opaque(WT_h), w1A = opaque(w1A_h), w4A = opaque(w4A_h);
+        const float2 w1B = opaque(w1B_h), w4B = opaque(w4B_h), w21 = opaque(w21_h), w24 = opaque(w24_h);
+        const int k2 = T & (R1 - 1);  // P2: j mod R1 = T mod R1
+        const int64_t r = g * ROWS + rho;
+        const bool live = r < a.rows;
+
+        float2 x[32];
+        // ---- P1 inputs: butterfly T + b TN reads elements j + t M/R1; those
+        // with t >= R1/2 are zero
+        if constexpr (PERSIST) {
+#pragma unroll
+            for (int b = 0; b < NB1; ++b)
+#pragma unroll
+                for (int t = 0; t < R1; ++t) x[b * R1 + t] = t < H1 ? xn[b * H1 + t] : make_float2(0.0f, 0.0f);
+        } else if constexpr (!PRE) {
+            float2 xl[NB1 * H1];
+            if (live) load_p1_any<R1, NB1, TN, M>(xl, a, in_t, r, T);
+            else
+#pragma unroll
+                for (int i = 0; i < NB1 * H1; ++i) xl[i] = make_float2(0.0f, 0.0f);
+#pragma unroll
+            for (int b = 0; b < NB1; ++b)
+#pragma unroll
+                for (int t = 0; t < R1; ++t) x[b * R1 + t] = t < H1 ? xl[b * H1 + t] : make_float2(0.0f, 0.0f);
+        } else {
+            // front end: Beer-Lambert of the row into LDS (plain floats), then
+            // the blurred samples of this thread's elements
+            const PreArgs &pre = a.pre;
+            float *stage = reinterpret_cast<float *>(z + rb);
+            if (live) {
+                const int64_t s = r / pre.n_angles;
+                const int64_t kp = r - s * pre.n_angles;
+                const int64_t det_row = pre.row_begin + s;
+                const int64_t src = (kp * pre.n_rows + det_row) * nc;
+                for (int j = T; j < nc; j += TN) {
+                    const float raw = in_t == XCT_U16 ? (float)static_cast<const uint16_t *>(a.in)[src + j]
+                                                      : static_cast<const float *>(a.in)[src + j];
+                    stage[j] = beer_lambert(raw, pre.dark[det_row * nc + j], pre.flat[det_row * nc + j], pre.floor);
+                }
+            }
+            __syncthreads();
+            const int R = pre.radius;
+#pragma unroll
+            for (int b = 0; b < NB1; ++b)
+#pragma unroll
+                for (int t = 0; t < R1; ++t) {
+                    const int e = T + b * TN + t * (M / R1);
+                    float v[2] = {0.0f, 0.0f};
+                    if (t < H1 && live && 2 * e < nc) {
+                        if (R == 0) {
+                            v[0] = stage[2 * e];
+                            if (2 * e + 1 < nc) v[1] = stage[2 * e + 1];
+                        } else if (2 * e >= R && 2 * e + 1 + R < nc) {
+                            for (int m = -R; m <= R; ++m) {
+                                const float w = pre.taps[m + R];
+                                v[0] = fmaf(w, stage[2 * e + m], v[0]);
+                                v[1] = fmaf(w, stage[2 * e + 1 + m], v[1]);
+                            }
+                        } else {
+#pragma unroll
+                            for (int h = 0; h < 2; ++h) {
+                                const int j = 2 * e + h;
+                                if (j < nc)
+                                    for (int m = -R; m <= R; ++m)
+                                        v[h] = fmaf(pre.taps[m + R], stage[min(max(j + m, 0), nc - 1)], v[h]);
+                            }
+                        }
+                    }
+                    x[b * R1 + t] = make_float2(v[0], v[1]);
+                }
+            __syncthreads();  // the staged row is read before P1 overwrites it
+        }
+
+        // ---- P1 (span 1): outputs s of butterfly j at positions R1 j + s
+        {
+            const int sb = 8 * lpos(rb + R1 * T);
+#pragma unroll
+            for (int b = 0; b < NB1; ++b) {
+                dft<R1, false>(x + b * R1);
+#pragma unroll
+                for (int s = 0; s < R1; ++s) lds_at(z, sb, b * R1 * TN + s) = x[b * R1 + dft_slot<R1>(s)];
+            }
+        }
+        // spectrum factors of the last pass's positions A + s NS and
+        // B + s NS, then the next group's samples: loads complete in order,
+        // so the wait for these factors does not wait for the prefetch
+        float HA[16], HB[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            HA[s] = a.H[A + s * NS];
+            HB[s] = a.H[B + s * NS];
+        }
+        const float HM = a.H[M];
+        if constexpr (PERSIST) {
+            const int64_t gn = g + gridDim.x, rn = gn * ROWS + rho;
+            if (gn < groups && rn < a.rows) load_p1<R1, NB1, TN, M, TP, 0>(xn, a, rn, T);
+        }
+        __syncthreads();
+
+        // ---- P2 (span R1): butterfly j = T + b TN reads j + t M/R2, writes
+        // (j - k) R2 + k + s R1 with k = j mod R1
+        if constexpr (R2 > 1) {
+            {
+                const int sb = 8 * lpos(rb + T);
+#pragma unroll
+                for (int b = 0; b < NB2; ++b)
+#pragma unroll
+                    for (int t = 0; t < R2; ++t) x[b * R2 + t] = lds_at(z, sb, b * TN + t * (M / R2));
+            }
+            __syncthreads();
+            float2 tw2[R2];
+            if constexpr (R2 == 16) {
+                powers16(w21, w24, tw2);
+            } else {
+                tw2[0] = make_float2(1.0f, 0.0f);
+                tw2[1] = w21;
+                tw2[2] = cmul(w21, w21);
+                tw2[3] = cmul(tw2[2], w21);
+            }
+#pragma unroll
+            for (int b = 0; b < NB2; ++b) {
+#pragma unroll
+                for (int t = 1; t < R2; ++t) x[b * R2 + t] = cmul(x[b * R2 + t], tw2[t]);
+                dft<R2, false>(x + b * R2);
+            }
+            const int sb = 8 * lpos(rb + (T - k2) * R2 + k2);
+#pragma unroll
+            for (int b = 0; b < NB2; ++b)
+#pragma unroll
+                for (int s = 0; s < R2; ++s) lds_at(z, sb, b * TN * R2 + s * R1) = x[b * R2 + dft_slot<R2>(s)];
+            __syncthreads();
+        }
+
+        // ---- P3 (span NS) on butterflies A and B, spectrum, P3^H
+        float2 *xa = x, *xb = x + 16;
+        {
+            const int sbA = 8 * lpos(rb + A), sbB = 8 * lpos(rb + B);
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                xa[t] = lds_at(z, sbA, t * NS);
+                xb[t] = lds_at(z, sbB, t * NS);
+            }
+        }
+        // no barrier: P3^H writes back exactly the positions this thread read
+        {
+            float2 pA[16], pB[16];
+            powers16(w1A, w4A, pA);
+            powers16(w1B, w4B, pB);
+#pragma unroll
+            for (int t = 1; t < 16; ++t) {
+                xa[t] = cmul(xa[t], pA[t]);
+                xb[t] = cmul(xb[t], pB[t]);
+            }
+        }
+        dft<16, false>(xa);
+        dft<16, false>(xb);
+        // Z at position A + s NS is xa[dft_slot<16>(s)]; Z' replaces it there.
+#define XA(s) xa[dft_slot<16>(s)]
+#define XB(s) xb[dft_slot<16>(s)]
+        if (T == 0) {
+            // butterfly 0: pairs (s NS, (16 - s) NS), with bins 0 and M/2
+            // paired with themselves (H[M]: the real row's Nyquist bin);
+            // butterfly NS/2: pairs (NS/2 + s NS, NS/2 + (15 - s) NS);
+            // W^(s NS) = exp(-2 pi i s / 32)
+            float2 d;
+            spectrum_pair(XA(0), XA(0), make_float2(1.0f, 0.0f), HA[0], HM, XA(0), d);
+            spectrum_pair(XA(8), XA(8), make_float2(0.0f, -1.0f), HA[8], HA[8], XA(8), d);
+#pragma unroll
+            for (int s = 1; s < 8; ++s)
+                spectrum_pair(XA(s), XA(16 - s), root<false>(s, 32), HA[s], HA[16 - s], XA(s), XA(16 - s));
+#pragma unroll
+            for (int s = 0; s < 8; ++s)
+                spectrum_pair(XB(s), XB(15 - s), root<false>(2 * s + 1, 64), HB[s], HB[15 - s], XB(s), XB(15 - s));
+        }
+        if (T != 0) {
+            // pairs (A + s NS, M - A - s NS = B + (15 - s) NS), W^(T + s NS)
+#pragma unroll
+            for (int s = 0; s < 16; ++s)
+                spectrum_pair(XA(s), XB(15 - s), turn<false>(WT, s, 32), HA[s], HB[15 - s], XA(s), XB(15 - s));
+        }
+        // P3^H: DFT^H over s (inputs in natural order), conj twiddles, to A + t NS
+        {
+            float2 ya[16], yb[16];
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                ya[s] = XA(s);
+                yb[s] = XB(s);
+            }
+#undef XA
+#undef XB
+            dft<16, true>(ya);
+            dft<16, true>(yb);
+            float2 pA[16], pB[16];
+            powers16(opaque(w1A), opaque(w4A), pA);
+            powers16(opaque(w1B), opaque(w4B), pB);
+            const int sbA = opaque_i(8 * lpos(rb + A)), sbB = opaque_i(8 * lpos(rb + B));
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const float2 va = ya[dft_slot<16>(t)], vb = yb[dft_slot<16>(t)];
+                lds_at(z, sbA, t * NS) = t ? cconj_mul(va, pA[t]) : va;
+                lds_at(z, sbB, t * NS) = t ? cconj_mul(vb, pB[t]) : vb;
+            }
+        }
+        __syncthreads();
+
+        // ---- P2^H
+        if constexpr (R2 > 1) {
+            {
+                const int sb = opaque_i(8 * lpos(rb + (T - k2) * R2 + k2));
+#pragma unroll
+                for (int b = 0; b < NB2; ++b)
+#pragma unroll
+                    for (int s = 0; s < R2; ++s) x[b * R2 + s] = lds_at(z, sb, b * TN * R2 + s * R1);
+            }
+            __syncthreads();
+            float2 tw2[R2];
+            if constexpr (R2 == 16) {
+                powers16(opaque(w21), opaque(w24), tw2);
+            } else {
+                const float2 w = opaque(w21);
+                tw2[0] = make_float2(1.0f, 0.0f);
+                tw2[1] = w;
+                tw2[2] = cmul(w, w);
+                tw2[3] = cmul(tw2[2], w);
+            }
+            const int sb = opaque_i(8 * lpos(rb + T));
+#pragma unroll
+            for (int b = 0; b < NB2; ++b) {
+                dft<R2, true>(x + b * R2);
+#pragma unroll
+                for (int t = 0; t < R2; ++t) {
+                    const float2 v = x[b * R2 + dft_slot<R2>(t)];
+                    lds_at(z, sb, b * TN + t * (M / R2)) = t ? cconj_mul(v, tw2[t]) : v;
+                }
+            }
+            __syncthreads();
+        }
+
+        // ---- P1^H: DFT^H of the R1 values at positions R1 j + s, to elements
+        // j + t M/R1 of the output row (element e = samples 2e, 2e + 1)
+        {
+            const int sb = opaque_i(8 * lpos(rb + R1 * T));
+#pragma unroll
+            for (int b = 0; b < NB1; ++b) {
+#pragma unroll
+                for (int s = 0; s < R1; ++s) x[b * R1 + s] = lds_at(z, sb, b * R1 * TN + s);
+                dft<R1, true>(x + b * R1);
+            }
+        }
+        // The next group's P1 writes the positions this thread's P1^H read
+        // and nothing else; only the front end's staging of a raw row
+        // (one group per workgroup) touches other threads' positions.
+        if constexpr (PRE) __syncthreads();
+        if (live) {
+            if (out_t == XCT_F32) store_p1<R1, NB1, TN, M, float>(x, a, r, T);
+            else if (out_t == XCT_F16) store_p1<R1, NB1, TN, M, f16_t>(x, a, r, T);
+            else store_p1<R1, NB1, TN, M, bf16_t>(x, a, r, T);
+        }
+    };
+    if constexpr (PERSIST) {
+        for (; g < groups; g += gridDim.x) group(g);
+    } else {
+        if (g < groups) group(g);
+    }
+}
+
 template <typename TI, typename TO, bool PRE>
 static hipError_t launch_typed(const FilterArgs &a, hipStream_t s)
 {
@@ -442,7 +1073,7 @@ static hipError_t launch_typed(const FilterArgs &a, hipStream_t s)
     const size_t lds = (size_t)(M + ((M / 8 + 1 + 31) & ~31)) * sizeof(float2);
     (void)hipGetLastError();  // report only what this launch does
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(filter_kernel<TI, TO, PRE>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(filter_small_kernel<TI, TO, PRE>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
@@ -452,7 +1083,7 @@ static hipError_t launch_typed(const FilterArgs &a, hipStream_t s)
     for (int64_t r0 = 0; r0 < a.rows; r0 += max_rows) {
         c.row_base = r0;
         const int64_t n = a.rows - r0 < max_rows ? a.rows - r0 : max_rows;
-        hipLaunchKernelGGL((filter_kernel<TI, TO, PRE>), dim3((unsigned)n), dim3(nt), lds, s, c);
+        hipLaunchKernelGGL((filter_small_kernel<TI, TO, PRE>), dim3((unsigned)n), dim3(nt), lds, s, c);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -467,8 +1098,48 @@ static hipError_t launch_out(const FilterArgs &a, int out_t, hipStream_t s)
     return launch_typed<TI, bf16_t, PRE>(a, s);
 }
 
+template <int KIND>
+static hipError_t launch_kind(int lg, unsigned n, const FilterArgs &a, int in_t, int out_t, hipStream_t s)
+{
+    switch (lg) {
+    case 8: hipLaunchKernelGGL((filter_fused_kernel<8, KIND>), dim3(n), dim3(256), 0, s, a, in_t, out_t); break;
+    case 9: hipLaunchKernelGGL((filter_fused_kernel<9, KIND>), dim3(n), dim3(256), 0, s, a, in_t, out_t); break;
+    case 10: hipLaunchKernelGGL((filter_fused_kernel<10, KIND>), dim3(n), dim3(256), 0, s, a, in_t, out_t); break;
+    case 11: hipLaunchKernelGGL((filter_fused_kernel<11, KIND>), dim3(n), dim3(256), 0, s, a, in_t, out_t); break;
+    case 12: hipLaunchKernelGGL((filter_fused_kernel<12, KIND>), dim3(n), dim3(256), 0, s, a, in_t, out_t); break;
+    default: hipLaunchKernelGGL((filter_fused_kernel<13, KIND>), dim3(n), dim3(256), 0, s, a, in_t, out_t); break;
+    }
+    return hipGetLastError();
+}
+
+// Rows of 256 <= M <= 8192.  Unshifted, unweighted rows of even length in
+// a buffer aligned to two samples take the persistent kernel: two workgroups
+// per CU (as many as the LDS holds), each walking its groups of rows with the
+// next group's samples in flight.  Other rows and the front end take a
+// workgroup per group (at most 2^32 - 1 work-items: N_c <= 8192 keeps the
+// groups of any valid call below that).
+static hipError_t launch_fused(const FilterArgs &a, bool pre, int in_t, int out_t, hipStream_t s)
+{
+    const int lg = a.log2L - 1;  // log2 M
+    const int rows_per_wg = 8192 >> lg;
+    const int64_t wgs = (a.rows + rows_per_wg - 1) / rows_per_wg;
+    const size_t esz = in_t == XCT_F32 ? 4 : 2;
+    const bool persist = !pre && !a.weight && a.in_first == 0 && (a.in_len & 1) == 0 &&
+                         reinterpret_cast<uintptr_t>(a.in) % (2 * esz) == 0;
+    const int64_t cap = persist ? 2 * (int64_t)device_cus() : (((int64_t)1 << 32) - 1) / 256;
+    if (!persist && wgs > cap) return hipErrorInvalidConfiguration;
+    const unsigned n = (unsigned)(wgs < cap ? wgs : cap);
+    (void)hipGetLastError();  // report only what this launch does
+    if (pre) return launch_kind<kFrontEnd>(lg, n, a, in_t, out_t, s);
+    if (!persist) return launch_kind<kRows>(lg, n, a, in_t, out_t, s);
+    if (in_t == XCT_F32) return launch_kind<kPersistF32>(lg, n, a, in_t, out_t, s);
+    if (in_t == XCT_F16) return launch_kind<kPersistF16>(lg, n, a, in_t, out_t, s);
+    return launch_kind<kPersistBF16>(lg, n, a, in_t, out_t, s);
+}
+
 hipError_t launch_filter(const FilterArgs &a, int in_t, int out_t, hipStream_t s)
 {
+    if (a.log2L - 1 >= 8) return launch_fused(a, false, in_t, out_t, s);
     if (in_t == XCT_F32) return launch_out<float, false>(a, out_t, s);
     if (in_t == XCT_F16) return launch_out<f16_t, false>(a, out_t, s);
     return launch_out<bf16_t, false>(a, out_t, s);
@@ -476,6 +1147,7 @@ hipError_t launch_filter(const FilterArgs &a, int in_t, int out_t, hipStream_t s
 
 hipError_t launch_front_end_filter(const FilterArgs &a, int in_t, int out_t, hipStream_t s)
 {
+    if (a.log2L - 1 >= 8) return launch_fused(a, true, in_t, out_t, s);
     if (in_t == XCT_U16) return launch_out<uint16_t, true>(a, out_t, s);
     return launch_out<float, true>(a, out_t, s);
 }

@@ -167,4 +167,6 @@ int reduce_blocks(int64_t n);
 
 hipError_t launch_fill_u32(unsigned int *p, int n, unsigned int v, hipStream_t s);
 
+int device_cus();  // compute units of the current device
+
 }  // namespace xct
