@@ -266,6 +266,20 @@ int xct_dot_f64(const float *a, const float *b, int64_t n, double *result, void 
 int xct_sqdist_f64(const float *a, const float *b, int64_t n, double *result, void *workspace,
                    size_t workspace_bytes, xct_stream stream);
 
+/* xct_dot_f64 without a workspace, for callers that cannot allocate (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same result bit for bit, with the
+ * partial sums in a library-owned device array of 1024 doubles (8 KiB) on
+ * each GPU it runs on, held until the process ends.  Every n >= 1 fits (a
+ * reduction has at most 1024 partial sums), so no size is refused for
+ * space.  Calls no hipMalloc, hipFree or allocating routine; the first call
+ * on a device looks up that device's array address once.  All calls on one
+ * GPU share its array: calls that overlap in time on one GPU (different
+ * streams or threads with no ordering between them) race.
+ *   a, b: device [n] FP32; result: DEVICE pointer to one double.
+ * Errors: XCT_EINVAL for null pointers or n <= 0; XCT_EHIP if HIP fails. */
+int xct_dot_f64_noalloc(const float *a, const float *b, int64_t n, double *result, xct_stream stream);
+
 /* Static description of a status code. */
 const char *xct_status_string(int status);
 /* XCT_VERSION of the loaded library. */

@@ -1020,6 +1020,18 @@ int xct_sqdist_f64(const float *a, const float *b, int64_t n, double *result, vo
     return reduce_common(a, b, n, result, workspace, workspace_bytes, 1, stream);
 }
 
+int xct_dot_f64_noalloc(const float *a, const float *b, int64_t n, double *result, xct_stream stream)
+{
+    if (!a || !b || !result || n <= 0) return XCT_EINVAL;
+    const int nb = reduce_blocks(n);
+    if (nb > reduce_scratch_doubles()) return XCT_ETOOBIG;  // cannot happen: the partial count is capped
+    double *partials = nullptr;
+    hipError_t e = reduce_scratch(&partials);
+    if (e != hipSuccess) return hip_fail(e);
+    e = launch_reduce(a, b, n, result, partials, nb, 0, (hipStream_t)stream);
+    return e == hipSuccess ? XCT_OK : hip_fail(e);
+}
+
 }  // extern "C"
 
 // Compute units of the current device (cached per device).

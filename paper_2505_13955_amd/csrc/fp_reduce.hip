@@ -21,6 +21,7 @@
 // (wavefront shuffles, then LDS), and one workgroup sums the partials in a
 // fixed order, so results are reproducible bit for bit.
 #include <cmath>
+#include <mutex>
 
 #include "xct_internal.h"
 
@@ -410,6 +411,37 @@ hipError_t launch_reduce(const float *a, const float *b, int64_t n, double *resu
     hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(kRedThreads), 0, s, partials, nblocks,
                        result);
     return hipGetLastError();
+}
+
+// Partial sums of the allocation-free dot product (xct_dot_f64_noalloc):
+// one array per device, kept until the process ends.  In host code this name
+// is not a device address; reduce_scratch() looks up each device's copy with
+// hipGetSymbolAddress (once per device, that device current) and the kernels
+// take that pointer.
+constexpr int kScratchDoubles = kRedMaxBlocks;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+static_assert(kScratchDoubles >= kRedMaxBlocks, "every reduction's partial sums fit the scratch array");
+
+int reduce_scratch_doubles() { return kScratchDoubles; }
+
+hipError_t reduce_scratch(double **out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *ptr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        ptr[dev] = static_cast<double *>(p);
+    }
+    *out = ptr[dev];
+    return hipSuccess;
 }
 
 __global__ void fill_u32_kernel(unsigned int *p, int n, unsigned int v)

@@ -164,6 +164,10 @@ hipError_t launch_forward(const FPArgs &a, int sl, hipStream_t s);
 hipError_t launch_reduce(const float *a, const float *b, int64_t n, double *result,
                          double *partials, int nblocks, int sqdist, hipStream_t s);
 int reduce_blocks(int64_t n);
+// The allocation-free reduction's partial sums: this device's copy of the
+// library's scratch array (looked up on first use), and its length.
+hipError_t reduce_scratch(double **out);
+int reduce_scratch_doubles();
 
 hipError_t launch_fill_u32(unsigned int *p, int n, unsigned int v, hipStream_t s);
 

@@ -72,6 +72,7 @@ EXPORTS = (
     "xct_fbp_batch",
     "xct_reduce_workspace_bytes",
     "xct_dot_f64",
+    "xct_dot_f64_noalloc",
     "xct_sqdist_f64",
     "xct_status_string",
     "xct_version",
@@ -109,6 +110,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "xct_fbp_batch": ([sp, i32, i32, i32, i32, vp, sz, vp], ctypes.c_int),
         "xct_reduce_workspace_bytes": ([i64], sz),
         "xct_dot_f64": ([vp, vp, i64, vp, vp, sz, vp], ctypes.c_int),
+        "xct_dot_f64_noalloc": ([vp, vp, i64, vp, vp], ctypes.c_int),
         "xct_sqdist_f64": ([vp, vp, i64, vp, vp, sz, vp], ctypes.c_int),
         "xct_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "xct_version": ([], ctypes.c_int),
@@ -360,6 +362,22 @@ def _reduce(name: str, a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
 def xct_dot_f64(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
     """sum (double)a * (double)b, as a 0-d float64 device tensor."""
     return _reduce("xct_dot_f64", a, b)
+
+
+def xct_dot_f64_noalloc(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+    """xct_dot_f64 into the caller's 0-d float64 device tensor `out`, with no
+    workspace (the library's per-device scratch array holds the partials)."""
+    lib = load_library()
+    if a.shape != b.shape:
+        raise ValueError("operands differ in shape")
+    pa = _dev(a, "a", (torch.float32,))
+    pb = _dev(b, "b", (torch.float32,))
+    po = _dev(out, "out", (torch.float64,))
+    if out.numel() != 1:
+        raise ValueError("out must hold one float64")
+    rc = lib.xct_dot_f64_noalloc(pa, pb, a.numel(), po, _stream(a))
+    _check("xct_dot_f64_noalloc", rc)
+    return out
 
 
 def xct_sqdist_f64(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:

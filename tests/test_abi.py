@@ -207,6 +207,9 @@ def test_reduce_validation(lib):
     assert lib.xct_dot_f64(FAKE, FAKE, 0, FAKE, FAKE, 8, None) == EINVAL
     assert lib.xct_dot_f64(FAKE, FAKE, 100, FAKE, FAKE, 0, None) == EWORKSPACE
     assert lib.xct_sqdist_f64(FAKE, FAKE, 100, FAKE, ctypes.c_void_p(0x1004), 8, None) == EWORKSPACE
+    assert lib.xct_dot_f64_noalloc(FAKE, FAKE, 0, FAKE, None) == EINVAL
+    assert lib.xct_dot_f64_noalloc(None, FAKE, 10, FAKE, None) == EINVAL
+    assert lib.xct_dot_f64_noalloc(FAKE, FAKE, 10, None, None) == EINVAL
 
 
 def test_binding_rejects_host_tensors():
@@ -254,3 +257,4 @@ def test_no_device_reports_hip_error(lib):
     assert lib.xct_backproject(ctypes.byref(g), 1, FAKE, 0, FAKE2, 1.0, 0, None) == -5
     assert lib.xct_forward_project(ctypes.byref(g), 1, FAKE, FAKE2, 1.0, 0, None) == -5
     assert lib.xct_dot_f64(FAKE, FAKE2, 10, FAKE, ctypes.c_void_p(0x10000), 8, None) == -5
+    assert lib.xct_dot_f64_noalloc(FAKE, FAKE2, 10, FAKE, None) == -5
