@@ -8,14 +8,16 @@
 // a bin's strip crosses at most floor(2/|A|) + 1 pixels, centred on
 //   v*(n, w) = (n - u0 - B w) / A.
 // A workgroup takes one block of up to 16 consecutive angles that share the
-// walk axis and one block of 256 bins (a thread per bin).  It walks the image
-// a few steps at a time: it stages into LDS, with coalesced reads, the
+// walk axis and one block of 256 bins; a thread takes one angle and 16
+// consecutive bins (16 angles x 4 bin groups per wavefront).  It walks the
+// image a few steps at a time: it stages into LDS, with coalesced reads, the
 // rectangle of pixels those strips can touch (zeros outside the image), then
-// every thread adds its taps for every angle of the block.  Per angle and
-// stage a thread anchors its crossing in FP64 and keeps an integer index plus
-// an FP32 offset below the staged rows' count, so the hat weights carry
-// rounding of the order of 2^-19 pixel.  Fixed summation order: the output is
-// deterministic.
+// every thread adds its taps for its 16 bins, and at the end the results go
+// out through LDS so that the stores run along bins.  Per stage a thread
+// anchors its first bin's crossing in FP64 and keeps an integer index plus an
+// FP32 offset below 16/|A| + the staged rows' count, so the hat weights
+// carry rounding of the order of 2^-18 pixel.  Fixed summation order: the
+// output is deterministic.
 //
 // Reductions: a fixed grid of workgroups accumulates FP64 partial sums
 // (wavefront shuffles, then LDS), and one workgroup sums the partials in a
@@ -54,16 +56,27 @@ template <> struct FPVec<4> {
     }
 };
 
+// Lanes of a wavefront: 16 angles of the block x 4 groups of 16 consecutive
+// bins; a thread accumulates its angle's 16 bins for SL slices.  Lanes that
+// read together are the block's angles at the same bins, whose taps lie a
+// few pixels apart (often at the same address); lanes one bin apart at one
+// angle would read pixels 1/|A| > 1 apart, which costs more LDS bank
+// conflicts.
 template <int SL>
 __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
 {
     typedef FPVec<SL> V;
     typedef typename V::T VT;
     constexpr int kStageBatch = SL == 1 ? 8 : 4;  // staged pixels in flight per thread
-    constexpr int kUnroll = SL == 1 ? 4 : 2;      // walk steps per unrolled body
+    constexpr int kBinsPerThread = 16;
+    constexpr int kOutPitch = kFPBins + 1;        // LDS floats per angle in the output transpose
+    static_assert(kFPAngles == 16 && kFPBins == 256, "lane layout: 16 angles x 4 bin groups x 4 wavefronts");
+    static_assert(kFPAngles * kOutPitch <= kFPLdsFloats, "output transpose fits the staging buffer");
     __shared__ VT tile[kFPLdsFloats / SL];
     __shared__ int2 range;  // (first staged cross index, staged width)
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int q = lane & 15;                       // angle of the block
     const int wg = a.block_base + (int)blockIdx.x;
     const int blk = wg / a.bin_blocks;
     const int bb = wg - blk * a.bin_blocks;
@@ -73,16 +86,21 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
     const int walk = B.walk, count = B.count, k0 = B.k0;
     const int nv = walk ? a.ny : a.nx, nw = walk ? a.nx : a.ny;
     const int n0 = bb * kFPBins;
-    const int n1 = min(n0 + kFPBins - 1, a.n_det - 1);
-    const int n = min(n0 + tid, a.n_det - 1);  // threads past the last bin shadow it
+    const int n1 = n0 + kFPBins - 1;  // the plan sizes stages for whole bin blocks
+    const int nb = n0 + wave * 64 + (lane >> 4) * kBinsPerThread;  // this thread's first bin
     const int64_t plane = (int64_t)a.nx * a.ny;
     const float *img = a.image + (int64_t)z0 * plane;
     const int pitch = a.pitch, rows = a.rows;
     const int lg_rows = __builtin_ctz(rows);
+    const bool on = q < count;
+    const FPAngle p = a.ang[k0 + (on ? q : 0)];
+    const float invA = (float)p.invA;
+    const bool three = p.taps <= 3 && p.absA <= 1.0f;  // hat two to three pixels wide
+    const float c2 = fmaf(-2.0f, p.absA, 1.0f);
 
-    VT acc[kFPAngles];
+    VT acc[kBinsPerThread];
 #pragma unroll
-    for (int q = 0; q < kFPAngles; ++q) acc[q] = V::zero();
+    for (int b = 0; b < kBinsPerThread; ++b) acc[b] = V::zero();
 
     for (int w0 = 0; w0 < nw; w0 += rows) {
         const int rc = min(rows, nw - w0);
@@ -92,11 +110,11 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
             // in (n, w), so its extremes sit at the corners
             double lo = 1e300, hi = -1e300;
             if (tid < 4 * count) {
-                const FPAngle p = a.ang[k0 + (tid >> 2)];
+                const FPAngle pc = a.ang[k0 + (tid >> 2)];
                 const double nn = (tid & 1) ? n1 : n0;
                 const double ww = (tid & 2) ? w0 + rc - 1 : w0;
-                const double vs = (nn - p.u0 - p.B * ww) * p.invA;
-                const double h = 1.0 / fabs(p.A);
+                const double vs = (nn - pc.u0 - pc.B * ww) * pc.invA;
+                const double h = 1.0 / fabs(pc.A);
                 lo = vs - h;
                 hi = vs + h;
             }
@@ -159,78 +177,81 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
         }
         __syncthreads();
 
+        // This thread's crossings: v*(nb + b, w0 + r) - vlo = rel0 + b/A + r dv,
+        // anchored once per stage in FP64 (integer part bi0, FP32 fraction f00)
+        // so that the FP32 offsets stay below 16/|A| + rows (~2^-18 pixel).
+        const double rel0 = ((double)nb - p.u0 - p.B * (double)w0) * p.invA - (double)vlo;
+        const int bi0 = (int)floor(rel0);
+        const float f00 = (float)(rel0 - (double)bi0);
+        {
+            // skip the stage when no strip of the wavefront reaches the image
+            const float e0 = f00 + (float)bi0, eb = 15.0f * invA, er = (float)(rc - 1) * p.dv;
+            const float lo = e0 + fminf(eb, 0.0f) + fminf(er, 0.0f);
+            const float hi = e0 + fmaxf(eb, 0.0f) + fmaxf(er, 0.0f);
+            const bool hits = on && hi + p.hw > (float)(-vlo) - 1.0f && lo - p.hw < (float)(nv - vlo);
+            if (__builtin_amdgcn_ballot_w64(hits) == 0) continue;
+        }
+        const VT *base = tile + bi0;
+        if (three) {
+            // taps at t <= 0, t + 1 (|t + 1| |A| <= 1) and t + 2 > 0 pixels
+            // from the crossing: the first and last weights need no absolute
+            // value, the middle one no clamp
+            for (int r = 0; r < rc; ++r) {
+                const float vr = fmaf((float)r, p.dv, f00);
+                const VT *row = base + r * pitch;
 #pragma unroll
-        for (int q = 0; q < kFPAngles; ++q) {
-            if (q < count) {
-                const FPAngle p = a.ang[k0 + q];
-                const double rel = ((double)n - p.u0 - p.B * (double)w0) * p.invA - (double)vlo;
-                // skip the stage for this angle when no bin of the wavefront
-                // has a strip that reaches the image in these walk steps
-                const float r0f = (float)rel, r1f = fmaf((float)(rc - 1), p.dv, r0f);
-                const bool hits = (n0 + tid < a.n_det) && fmaxf(r0f, r1f) + p.hw > (float)(-vlo) - 1.0f &&
-                                  fminf(r0f, r1f) - p.hw < (float)(nv - vlo);
-                if (__builtin_amdgcn_ballot_w64(hits) == 0) continue;
-                const int bi = (int)floor(rel);
-                const float f0 = (float)(rel - (double)bi);
-                const VT *base = tile + bi;
-                VT s = acc[q];
-                int r = 0;
-                if (p.taps <= 3 && p.absA <= 1.0f) {
-                    // hat two to three pixels wide (2/3 < |A| <= 1): the taps
-                    // sit at t <= 0, t + 1 (|t + 1| |A| <= 1) and t + 2 > 0
-                    // pixels from the crossing, so their weights need no
-                    // absolute value (first, last) or clamp (middle)
-                    const float c2 = fmaf(-2.0f, p.absA, 1.0f);
-                    for (; r + kUnroll <= rc; r += kUnroll) {
-                        float t[kUnroll];
-                        VT x[kUnroll][3];
-#pragma unroll
-                        for (int u = 0; u < kUnroll; ++u) {
-                            const float vloc = fmaf((float)(r + u), p.dv, f0);
-                            const float vl = ceilf(vloc - p.hw);
-                            t[u] = vl - vloc;
-                            const VT *src = base + (r + u) * pitch + (int)vl;
-#pragma unroll
-                            for (int m = 0; m < 3; ++m) x[u][m] = src[m];
-                        }
-#pragma unroll
-                        for (int u = 0; u < kUnroll; ++u) {
-                            const float w0 = fmaxf(fmaf(p.absA, t[u], 1.0f), 0.0f);
-                            const float w1 = fmaf(-p.absA, fabsf(t[u] + 1.0f), 1.0f);
-                            const float w2 = fmaxf(fmaf(-p.absA, t[u], c2), 0.0f);
-                            s = V::fma(w0, x[u][0], s);
-                            s = V::fma(w1, x[u][1], s);
-                            s = V::fma(w2, x[u][2], s);
-                        }
-                    }
-                }
-                for (; r < rc; ++r) {
-                    const float vloc = fmaf((float)r, p.dv, f0);
+                for (int b = 0; b < kBinsPerThread; ++b) {
+                    const float vloc = fmaf((float)b, invA, vr);
                     const float vl = ceilf(vloc - p.hw);
                     const float t = vl - vloc;
-                    const VT *src = base + r * pitch + (int)vl;
+                    const VT *src = row + (int)vl;
+                    const VT x0 = src[0], x1 = src[1], x2 = src[2];
+                    const float w0 = fmaxf(fmaf(p.absA, t, 1.0f), 0.0f);
+                    const float w1 = fmaf(-p.absA, fabsf(t + 1.0f), 1.0f);
+                    const float w2 = fmaxf(fmaf(-p.absA, t, c2), 0.0f);
+                    acc[b] = V::fma(w0, x0, acc[b]);
+                    acc[b] = V::fma(w1, x1, acc[b]);
+                    acc[b] = V::fma(w2, x2, acc[b]);
+                }
+            }
+        } else {
+            for (int r = 0; r < rc; ++r) {
+                const float vr = fmaf((float)r, p.dv, f00);
+                const VT *row = base + r * pitch;
+#pragma unroll
+                for (int b = 0; b < kBinsPerThread; ++b) {
+                    const float vloc = fmaf((float)b, invA, vr);
+                    const float vl = ceilf(vloc - p.hw);
+                    const float t = vl - vloc;
+                    const VT *src = row + (int)vl;
                     for (int m = 0; m < p.taps; ++m) {
                         const float wgt = fmaxf(fmaf(-p.absA, fabsf(t + (float)m), 1.0f), 0.0f);
-                        s = V::fma(wgt, src[m], s);
+                        acc[b] = V::fma(wgt, src[m], acc[b]);
                     }
                 }
-                acc[q] = s;
             }
         }
     }
 
-    if (n0 + tid < a.n_det) {
+    // Output through LDS, one slice at a time, so that each wavefront stores
+    // whole runs of consecutive bins: [angle][bin] with a pitch of 257 floats
+    // (the 16 angles x 4 bin groups of a write meet distinct banks).
+    float *out_lds = reinterpret_cast<float *>(tile);
 #pragma unroll
-        for (int q = 0; q < kFPAngles; ++q) {
-            if (q < count) {
+    for (int sl = 0; sl < SL; ++sl) {
+        if (sl >= nsl) break;
+        __syncthreads();
 #pragma unroll
-                for (int sl = 0; sl < SL; ++sl) {
-                    if (sl < nsl) {
-                        float *out = a.sino + ((int64_t)(z0 + sl) * a.n_angles + k0 + q) * a.n_det + n0 + tid;
-                        const float v = V::get(acc[q], sl);
-                        *out = a.accumulate ? fmaf(a.scale, v, *out) : a.scale * v;
-                    }
-                }
+        for (int b = 0; b < kBinsPerThread; ++b)
+            out_lds[q * kOutPitch + (nb - n0) + b] = V::get(acc[b], sl);
+        __syncthreads();
+        const int n = n0 + tid;
+        if (n < a.n_det) {
+            float *out = a.sino + ((int64_t)(z0 + sl) * a.n_angles + k0) * a.n_det + n;
+            for (int qq = 0; qq < count; ++qq) {
+                const float v = out_lds[qq * kOutPitch + tid];
+                float *o = out + (int64_t)qq * a.n_det;
+                *o = a.accumulate ? fmaf(a.scale, v, *o) : a.scale * v;
             }
         }
     }
