@@ -831,42 +831,85 @@ __global__ __launch_bounds__(256) void filter_fused_kernel(FilterArgs a, int in_
                 const int64_t kp = r - s * pre.n_angles;
                 const int64_t det_row = pre.row_begin + s;
                 const int64_t src = (kp * pre.n_rows + det_row) * nc;
-                for (int j = T; j < nc; j += TN) {
-                    const float raw = in_t == XCT_U16 ? (float)static_cast<const uint16_t *>(a.in)[src + j]
-                                                      : static_cast<const float *>(a.in)[src + j];
-                    stage[j] = beer_lambert(raw, pre.dark[det_row * nc + j], pre.flat[det_row * nc + j], pre.floor);
+                const float *drow = pre.dark + det_row * nc, *frow = pre.flat + det_row * nc;
+                // a row has at most M = 32 TN samples: 32 per thread, loads
+                // issued eight samples at a time
+#pragma unroll
+                for (int j0 = 0; j0 < 32; j0 += 8) {
+                    float raw[8], dk[8], fl[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int j = T + (j0 + u) * TN;
+                        const int jc = j < nc ? j : 0;
+                        raw[u] = in_t == XCT_U16 ? (float)static_cast<const uint16_t *>(a.in)[src + jc]
+                                                 : static_cast<const float *>(a.in)[src + jc];
+                        dk[u] = drow[jc];
+                        fl[u] = frow[jc];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int j = T + (j0 + u) * TN;
+                        if (j < nc) stage[j] = beer_lambert(raw[u], dk[u], fl[u], pre.floor);
+                    }
                 }
             }
             __syncthreads();
             const int R = pre.radius;
+            const int K = (R + 1) >> 1;  // sample pairs each side of an element
 #pragma unroll
-            for (int b = 0; b < NB1; ++b)
+            for (int i = 0; i < 32; ++i) x[i] = make_float2(0.0f, 0.0f);
+            if (R == 0) {
 #pragma unroll
-                for (int t = 0; t < R1; ++t) {
-                    const int e = T + b * TN + t * (M / R1);
-                    float v[2] = {0.0f, 0.0f};
-                    if (t < H1 && live && 2 * e < nc) {
-                        if (R == 0) {
-                            v[0] = stage[2 * e];
-                            if (2 * e + 1 < nc) v[1] = stage[2 * e + 1];
-                        } else if (2 * e >= R && 2 * e + 1 + R < nc) {
-                            for (int m = -R; m <= R; ++m) {
-                                const float w = pre.taps[m + R];
-                                v[0] = fmaf(w, stage[2 * e + m], v[0]);
-                                v[1] = fmaf(w, stage[2 * e + 1 + m], v[1]);
+                for (int b = 0; b < NB1; ++b)
+#pragma unroll
+                    for (int t = 0; t < H1; ++t) {
+                        const int e = T + b * TN + t * (M / R1);
+                        if (live && 2 * e < nc)
+                            x[b * R1 + t] = make_float2(stage[2 * e], 2 * e + 1 < nc ? stage[2 * e + 1] : 0.0f);
+                    }
+            } else {
+                // Interior elements (every tap inside the row): pairs q_k =
+                // (s[2e + 2k], s[2e + 2k + 1]), |k| <= K, cover samples
+                // 2e - R .. 2e + 1 + R; bin 2e takes weights w(2k), w(2k + 1),
+                // bin 2e + 1 takes w(2k - 1), w(2k) (w zero beyond |m| = R).
+                // The weights are uniform: read once per pair offset.
+                const float2 *pairs = reinterpret_cast<const float2 *>(stage);
+                for (int k = -K; k <= K; ++k) {
+                    const int m0 = 2 * k;
+                    const float wm = m0 - 1 >= -R ? pre.taps[m0 - 1 + R] : 0.0f;  // m0 - 1 <= R always
+                    const float w0 = (m0 >= -R && m0 <= R) ? pre.taps[m0 + R] : 0.0f;
+                    const float wp = m0 + 1 <= R ? pre.taps[m0 + 1 + R] : 0.0f;   // m0 + 1 >= -R always
+#pragma unroll
+                    for (int b = 0; b < NB1; ++b)
+#pragma unroll
+                        for (int t = 0; t < H1; ++t) {
+                            const int e = T + b * TN + t * (M / R1);
+                            if (live && e >= K && 2 * e + 1 + 2 * K < nc) {
+                                const float2 q = pairs[e + k];
+                                float2 &v = x[b * R1 + t];
+                                v.x = fmaf(w0, q.x, fmaf(wp, q.y, v.x));
+                                v.y = fmaf(wm, q.x, fmaf(w0, q.y, v.y));
                             }
-                        } else {
+                        }
+                }
+                // elements near the row's ends: edge samples replicated
 #pragma unroll
+                for (int b = 0; b < NB1; ++b)
+#pragma unroll
+                    for (int t = 0; t < H1; ++t) {
+                        const int e = T + b * TN + t * (M / R1);
+                        if (live && 2 * e < nc && !(e >= K && 2 * e + 1 + 2 * K < nc)) {
+                            float v[2] = {0.0f, 0.0f};
                             for (int h = 0; h < 2; ++h) {
                                 const int j = 2 * e + h;
                                 if (j < nc)
                                     for (int m = -R; m <= R; ++m)
                                         v[h] = fmaf(pre.taps[m + R], stage[min(max(j + m, 0), nc - 1)], v[h]);
                             }
+                            x[b * R1 + t] = make_float2(v[0], v[1]);
                         }
                     }
-                    x[b * R1 + t] = make_float2(v[0], v[1]);
-                }
+            }
             __syncthreads();  // the staged row is read before P1 overwrites it
         }
 
