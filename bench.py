@@ -47,9 +47,9 @@ HBM_PEAK_GBPS = 8000.0
 # HBM bytes of one FP32 back-projection launch of the full 16-slice slab:
 # rocprofv3 FETCH_SIZE x 2.0 plus WRITE_SIZE x 1.0 (the factors under which a
 # plain 1 GiB device copy reads and writes 1 GiB), from the counter passes in
-# profiles/bp_sym_kernel_slab16_8192.txt.  None while no counter pass has been
-# taken on the current kernel build.
-BP_TRAFFIC_BYTES = None
+# profiles/bp_sym_kernel_slab16_8192.txt (None while no counter pass has been
+# taken on the current kernel build).
+BP_TRAFFIC_BYTES = 9.887e10
 
 
 def parse():
