@@ -142,7 +142,9 @@ int xct_filter_offset(const xct_geometry *g, int32_t n_slices, const void *sino,
  * the projection stack as acquired into one sinogram per detector row:
  *   p[s][k][n]  = -ln(max(I - D, floor) / max(F - D, floor)),
  *                 I = proj[k][row_begin + s][n], D = dark[row_begin + s][n],
- *                 F = flat[row_begin + s][n]                      (FP32 logf)
+ *                 F = flat[row_begin + s][n]                      (FP32 logf;
+ *                 the quotient by the hardware reciprocal of F - D, taken
+ *                 at most 2^126)
  *   b[s][k][n]  = sum_{|m| <= R} g[m] p[s][k][clamp(n + m, 0, N_c - 1)],
  *                 g[m] = exp(-m^2 / (2 sigma^2)) / sum, R = int(4 sigma + 0.5)
  *                 (sigma = 0: b = p)
@@ -153,7 +155,8 @@ int xct_filter_offset(const xct_geometry *g, int32_t n_slices, const void *sino,
  *              must not overlap proj
  * Rows row_begin .. row_begin + n_slices - 1 of the detector are processed
  * (a slab of the scan).  Errors: XCT_EINVAL for null pointers, a row range
- * outside [0, n_rows), floor <= 0, sigma < 0 or non-finite; XCT_ETOOBIG for
+ * outside [0, n_rows), floor below FLT_MIN (the smallest normal float),
+ * sigma < 0 or non-finite; XCT_ETOOBIG for
  * R > 64 (sigma >= 16.125) or N_c > 8192; XCT_EDTYPE for other dtypes. */
 int xct_preprocess_filter(const xct_geometry *g, int32_t n_rows, int32_t row_begin, int32_t n_slices,
                           const void *proj, int32_t proj_t, const float *dark, const float *flat,

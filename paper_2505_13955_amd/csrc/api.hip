@@ -5,6 +5,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -736,7 +737,7 @@ int xct_preprocess_filter(const xct_geometry *g, int32_t n_rows, int32_t row_beg
     if (!proj || !dark || !flat || !filtered) return XCT_EINVAL;
     if ((proj_t != XCT_U16 && proj_t != XCT_F32) || !dtype_ok(filtered_t)) return XCT_EDTYPE;
     if (window < XCT_RAM_LAK || window > XCT_HANN) return XCT_EDTYPE;
-    if (!std::isfinite(floor) || !(floor > 0.0f)) return XCT_EINVAL;
+    if (!std::isfinite(floor) || !(floor >= std::numeric_limits<float>::min())) return XCT_EINVAL;
     if (!std::isfinite(blur_sigma) || blur_sigma < 0.0f) return XCT_EINVAL;
     if (g->n_det > kMaxFFT / 2) return XCT_ETOOBIG;
     if ((double)g->n_angles * n_rows * g->n_det > 4.0e18) return XCT_ETOOBIG;

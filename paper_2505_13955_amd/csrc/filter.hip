@@ -280,9 +280,11 @@ __device__ __forceinline__ void fft_forward(float2 *z, int L, int log2L, const f
 
 // Line integral of one raw detector sample (Beer-Lambert, Section V-A c
 // stage 2): -ln((I - D) / (F - D)), both differences clamped below at `floor`.
+// The quotient takes the hardware reciprocal (about one ulp) of F - D, which
+// floor >= the smallest normal float and the cap at 2^126 keep normal.
 __device__ __forceinline__ float beer_lambert(float i, float d, float f, float floor)
 {
-    return -logf(fmaxf(i - d, floor) / fmaxf(f - d, floor));
+    return -logf(fmaxf(i - d, floor) * __builtin_amdgcn_rcpf(fminf(fmaxf(f - d, floor), 0x1p126f)));
 }
 
 // Front end of one row: row r of the output is detector row row_begin + s of
@@ -731,16 +733,109 @@ __device__ __forceinline__ void store_p1(const float2 *x, const FilterArgs &a, i
         }
 }
 
+// Persistent front end: a raw uint16 row of N_c = 4 n_q counts is read in
+// quads (8 bytes); thread T of a row takes quads T + i TN, i < 8 (8 TN = M/4
+// quads cover any N_c <= M).  Quads past the row re-read the row's last quad
+// (in bounds); those values are never used.
+__device__ __forceinline__ float4 quad_f32(uint2 v)
+{
+    return make_float4((float)(v.x & 0xffffu), (float)(v.x >> 16), (float)(v.y & 0xffffu), (float)(v.y >> 16));
+}
+
+template <int TN>
+__device__ __forceinline__ void load_raw_quads(uint2 (&q)[8], const FilterArgs &a, int64_t r, int T)
+{
+    const PreArgs &pre = a.pre;
+    const int64_t s = r / pre.n_angles, kp = r - s * pre.n_angles;
+    const uint2 *row = reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(a.in) +
+                                                       (kp * pre.n_rows + pre.row_begin + s) * a.nc);
+    const int last = (a.nc >> 2) - 1;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) q[i] = row[min(T + i * TN, last)];
+}
+
+// Gaussian blur (taps w[-R..R], edge samples replicated) of a staged row of
+// N_c = 4 n_q samples from src into dst, by quads: thread T of the row takes
+// quads T + i TN, i < 8.  A quad whose taps stay inside the row reads its
+// neighbour quads as 16-byte words; the quads within R samples of an end
+// read clamped samples one at a time.
+template <int TN>
+__device__ __forceinline__ void blur_quads(const float *src, float *dst, int nc, int R, const float *w, int T)
+{
+    const int nq = nc >> 2;
+    const int QR = (R + 3) >> 2;  // neighbour quads each side
+    const float4 *s4 = reinterpret_cast<const float4 *>(src);
+    float4 *d4 = reinterpret_cast<float4 *>(dst);
+    auto edge = [&](int q) {
+        float o[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int m = -R; m <= R; ++m) {
+            const float wm = w[m + R];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) o[c] = fmaf(wm, src[min(max(4 * q + c + m, 0), nc - 1)], o[c]);
+        }
+        d4[q] = make_float4(o[0], o[1], o[2], o[3]);
+    };
+    if (R <= 4) {
+        // taps padded to w[-4..4]: three quads q - 1, q, q + 1 cover them
+        float tk[9];
+#pragma unroll
+        for (int m = -4; m <= 4; ++m) tk[m + 4] = (m >= -R && m <= R) ? w[min(max(m + R, 0), 2 * R)] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int q = T + i * TN;
+            if (q >= nq) continue;
+            if (q >= 1 && q + 1 < nq) {
+                const float4 a = s4[q - 1], b = s4[q], c = s4[q + 1];
+                const float v[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+                float o[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int m = -4; m <= 4; ++m)
+#pragma unroll
+                    for (int cc = 0; cc < 4; ++cc) o[cc] = fmaf(tk[m + 4], v[4 + cc + m], o[cc]);
+                d4[q] = make_float4(o[0], o[1], o[2], o[3]);
+            } else {
+                edge(q);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int q = T + i * TN;
+            if (q >= nq) continue;
+            if (q >= QR && q + QR < nq) {
+                float o[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                for (int j = -QR; j <= QR; ++j) {
+                    const float4 u = s4[q + j];
+                    const float v[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                    for (int cc = 0; cc < 4; ++cc)
+#pragma unroll
+                        for (int cp = 0; cp < 4; ++cp) {
+                            const int m = 4 * j + cp - cc;
+                            if (m >= -R && m <= R) o[cc] = fmaf(w[m + R], v[cp], o[cc]);
+                        }
+                }
+                d4[q] = make_float4(o[0], o[1], o[2], o[3]);
+            } else {
+                edge(q);
+            }
+        }
+    }
+}
+
 // Kernel kinds: the front end (raw projection stack); any row form with one
-// workgroup per group of rows; and persistent kernels for unshifted,
-// unweighted rows of even length in FP32, FP16 or BF16 that keep the next
-// group's samples in flight.
-enum { kFrontEnd = 0, kRows = 1, kPersistF32 = 2, kPersistF16 = 3, kPersistBF16 = 4 };
+// workgroup per group of rows; persistent kernels for unshifted, unweighted
+// rows of even length in FP32, FP16 or BF16 that keep the next group's
+// samples in flight; and a persistent front end (uint16 counts, N_c a
+// multiple of 4, stack and fields aligned to quads) that keeps the next
+// group's counts in flight.
+enum { kFrontEnd = 0, kRows = 1, kPersistF32 = 2, kPersistF16 = 3, kPersistBF16 = 4, kPersistFE16 = 5 };
 
 template <int LOG2M, int KIND>
 __global__ __launch_bounds__(256) void filter_fused_kernel(FilterArgs a, int in_t, int out_t)
 {
-    constexpr bool PRE = KIND == kFrontEnd;
+    constexpr bool FEP = KIND == kPersistFE16;
+    constexpr bool PRE = KIND == kFrontEnd || FEP;
     constexpr bool PERSIST = KIND >= kPersistF32;
     typedef typename std::conditional<KIND == kPersistF16, f16_t,
                                       typename std::conditional<KIND == kPersistBF16, bf16_t, float>::type>::type TP;
@@ -754,7 +849,7 @@ __global__ __launch_bounds__(256) void filter_fused_kernel(FilterArgs a, int in_
     constexpr int TN = M / 32;         // threads per row
     constexpr int ROWS = 256 / TN;     // rows per workgroup
     static_assert(LOG2M >= 8 && LOG2M <= 13, "fused filter: 256 <= M <= 8192");
-    __shared__ float2 z[8192];
+    __shared__ __align__(16) float2 z[8192];
 
     const int tid = threadIdx.x;
     const int rho = tid / TN, T_h = tid % TN;
@@ -780,8 +875,12 @@ __global__ __launch_bounds__(256) void filter_fused_kernel(FilterArgs a, int in_
     // The plain filter holds the next group's P1 inputs in xn while the
     // current group is transformed.
     float2 xn[NB1 * H1];
+    uint2 rq[8];
     int64_t g = blockIdx.x;
-    if constexpr (PERSIST) {
+    if constexpr (FEP) {
+        const int64_t r = g * ROWS + rho;
+        if (g < groups && r < a.rows) load_raw_quads<TN>(rq, a, r, T_h);
+    } else if constexpr (PERSIST) {
         const int64_t r = g * ROWS + rho;
         if (g < groups && r < a.rows) load_p1<R1, NB1, TN, M, TP, 0>(xn, a, r, T_h);
         else
@@ -806,7 +905,7 @@ __global__ __launch_bounds__(256) void filter_fused_kernel(FilterArgs a, int in_
         float2 x[32];
         // ---- P1 inputs: butterfly T + b TN reads elements j + t M/R1; those
         // with t >= R1/2 are zero
-        if constexpr (PERSIST) {
+        if constexpr (PERSIST && !FEP) {
 #pragma unroll
             for (int b = 0; b < NB1; ++b)
 #pragma unroll
@@ -826,7 +925,32 @@ __global__ __launch_bounds__(256) void filter_fused_kernel(FilterArgs a, int in_
             // the blurred samples of this thread's elements
             const PreArgs &pre = a.pre;
             float *stage = reinterpret_cast<float *>(z + rb);
-            if (live) {
+            if (FEP && live) {
+                // the row's raw quads are in rq; its dark and flat quads
+                // are read here (the fields stay in L2)
+                const int64_t det_row = pre.row_begin + r / pre.n_angles;
+                const float4 *d4 = reinterpret_cast<const float4 *>(pre.dark + det_row * nc);
+                const float4 *f4 = reinterpret_cast<const float4 *>(pre.flat + det_row * nc);
+                const int nq = nc >> 2;
+                float4 dk[8], fl[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int q = min(T + i * TN, nq - 1);
+                    dk[i] = d4[q];
+                    fl[i] = f4[q];
+                }
+                float4 *st4 = reinterpret_cast<float4 *>(stage);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int q = T + i * TN;
+                    const float4 v = quad_f32(rq[i]);
+                    if (q < nq)
+                        st4[q] = make_float4(beer_lambert(v.x, dk[i].x, fl[i].x, pre.floor),
+                                             beer_lambert(v.y, dk[i].y, fl[i].y, pre.floor),
+                                             beer_lambert(v.z, dk[i].z, fl[i].z, pre.floor),
+                                             beer_lambert(v.w, dk[i].w, fl[i].w, pre.floor));
+                }
+            } else if (live) {
                 const int64_t s = r / pre.n_angles;
                 const int64_t kp = r - s * pre.n_angles;
                 const int64_t det_row = pre.row_begin + s;
@@ -858,7 +982,24 @@ __global__ __launch_bounds__(256) void filter_fused_kernel(FilterArgs a, int in_
             const int K = (R + 1) >> 1;  // sample pairs each side of an element
 #pragma unroll
             for (int i = 0; i < 32; ++i) x[i] = make_float2(0.0f, 0.0f);
-            if (R == 0) {
+            if constexpr (FEP) {
+                // blurred row into the upper half of the row's region
+                // (N_c <= M floats each), then the elements' sample pairs
+                const float *src = stage;
+                if (R > 0) {
+                    if (live) blur_quads<TN>(stage, stage + M, nc, R, pre.taps, T);
+                    __syncthreads();
+                    src = stage + M;
+                }
+                const float2 *p2 = reinterpret_cast<const float2 *>(src);
+#pragma unroll
+                for (int b = 0; b < NB1; ++b)
+#pragma unroll
+                    for (int t = 0; t < H1; ++t) {
+                        const int e = T + b * TN + t * (M / R1);
+                        if (live && 2 * e < nc) x[b * R1 + t] = p2[e];
+                    }
+            } else if (R == 0) {
 #pragma unroll
                 for (int b = 0; b < NB1; ++b)
 #pragma unroll
@@ -933,7 +1074,10 @@ __global__ __launch_bounds__(256) void filter_fused_kernel(FilterArgs a, int in_
             HB[s] = a.H[B + s * NS];
         }
         const float HM = a.H[M];
-        if constexpr (PERSIST) {
+        if constexpr (FEP) {
+            const int64_t gn = g + gridDim.x, rn = gn * ROWS + rho;
+            if (gn < groups && rn < a.rows) load_raw_quads<TN>(rq, a, rn, T);
+        } else if constexpr (PERSIST) {
             const int64_t gn = g + gridDim.x, rn = gn * ROWS + rho;
             if (gn < groups && rn < a.rows) load_p1<R1, NB1, TN, M, TP, 0>(xn, a, rn, T);
         }
@@ -1091,7 +1235,7 @@ __global__ __launch_bounds__(256) void filter_fused_kernel(FilterArgs a, int in_
         }
         // The next group's P1 writes the positions this thread's P1^H read
         // and nothing else; only the front end's staging of a raw row
-        // (one group per workgroup) touches other threads' positions.
+        // touches other threads' positions.
         if constexpr (PRE) __syncthreads();
         if (live) {
             if (out_t == XCT_F32) store_p1<R1, NB1, TN, M, float>(x, a, r, T);
@@ -1156,23 +1300,28 @@ static hipError_t launch_kind(int lg, unsigned n, const FilterArgs &a, int in_t,
 }
 
 // Rows of 256 <= M <= 8192.  Unshifted, unweighted rows of even length in
-// a buffer aligned to two samples take the persistent kernel: two workgroups
-// per CU (as many as the LDS holds), each walking its groups of rows with the
-// next group's samples in flight.  Other rows and the front end take a
-// workgroup per group (at most 2^32 - 1 work-items: N_c <= 8192 keeps the
-// groups of any valid call below that).
+// a buffer aligned to two samples, and front ends from uint16 counts over N_c
+// a multiple of 4 with the stack aligned to 8 bytes and the fields to 16, take a
+// persistent kernel: two workgroups per CU (as many as the LDS holds), each
+// walking its groups of rows with the next group's samples in flight.  Other
+// rows take a workgroup per group (at most 2^32 - 1 work-items: N_c <= 8192
+// keeps the groups of any valid call below that).
 static hipError_t launch_fused(const FilterArgs &a, bool pre, int in_t, int out_t, hipStream_t s)
 {
     const int lg = a.log2L - 1;  // log2 M
     const int rows_per_wg = 8192 >> lg;
     const int64_t wgs = (a.rows + rows_per_wg - 1) / rows_per_wg;
     const size_t esz = in_t == XCT_F32 ? 4 : 2;
-    const bool persist = !pre && !a.weight && a.in_first == 0 && (a.in_len & 1) == 0 &&
-                         reinterpret_cast<uintptr_t>(a.in) % (2 * esz) == 0;
+    const bool persist = pre ? in_t == XCT_U16 && (a.nc & 3) == 0 && reinterpret_cast<uintptr_t>(a.in) % 8 == 0 &&
+                                   reinterpret_cast<uintptr_t>(a.pre.dark) % 16 == 0 &&
+                                   reinterpret_cast<uintptr_t>(a.pre.flat) % 16 == 0
+                             : !a.weight && a.in_first == 0 && (a.in_len & 1) == 0 &&
+                                   reinterpret_cast<uintptr_t>(a.in) % (2 * esz) == 0;
     const int64_t cap = persist ? 2 * (int64_t)device_cus() : (((int64_t)1 << 32) - 1) / 256;
     if (!persist && wgs > cap) return hipErrorInvalidConfiguration;
     const unsigned n = (unsigned)(wgs < cap ? wgs : cap);
     (void)hipGetLastError();  // report only what this launch does
+    if (pre && persist) return launch_kind<kPersistFE16>(lg, n, a, in_t, out_t, s);
     if (pre) return launch_kind<kFrontEnd>(lg, n, a, in_t, out_t, s);
     if (!persist) return launch_kind<kRows>(lg, n, a, in_t, out_t, s);
     if (in_t == XCT_F32) return launch_kind<kPersistF32>(lg, n, a, in_t, out_t, s);

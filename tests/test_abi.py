@@ -121,6 +121,7 @@ def test_preprocess_filter_validation(lib):
     assert call(n_rows=0) == EINVAL
     assert call(n_slices=0) == EINVAL
     assert call(floor=0.0) == EINVAL
+    assert call(floor=1e-39) == EINVAL               # below the smallest normal float
     assert call(floor=float("nan")) == EINVAL
     assert call(sigma=-0.5) == EINVAL
     assert call(sigma=float("inf")) == EINVAL

@@ -197,6 +197,13 @@ FE_CASES = [
     (6, 2, 8192, 0, 2, 1.0, torch.uint16, torch.float32, "hann"),   # widest detector
     (9, 2, 1, 0, 2, 0.5, torch.float32, torch.float32, "ram_lak"),  # one channel
     (11, 3, 40, 0, 3, 15.0, torch.uint16, torch.float32, "ram_lak"),  # blur wider than the row
+    # uint16 counts over N_c a multiple of 4 take the persistent front end:
+    # 600 rows of 8192 (more rows than one pass of the grid), 18,000 rows of
+    # 256 in groups of 32 (563 groups), and a row count that leaves the last
+    # group partial
+    (300, 2, 8192, 0, 2, 1.0, torch.uint16, torch.float32, "hann"),
+    (6000, 3, 256, 0, 3, 1.0, torch.uint16, torch.float32, "ram_lak"),
+    (4001, 4, 1024, 2, 2, 2.0, torch.uint16, torch.bfloat16, "shepp_logan"),
 ]
 
 
