@@ -207,7 +207,8 @@ int xct_backproject_u16(const xct_geometry *g, int32_t n_slices, const void *sin
  * operator is the differentiable pair's forward half.
  *   image  device [n_slices][N_y][N_x] FP32;  sino  device [n_slices][N_p][N_c] FP32
  * Deterministic (gather form, no atomics).  Errors: XCT_EINVAL for
- * non-finite alpha, XCT_ETOOBIG beyond 65535 slices. */
+ * non-finite alpha, XCT_ETOOBIG beyond 65535 slices or 2^31 workgroups
+ * (one per group of four slices, 256 bins and up to 16 angles). */
 int xct_forward_project(const xct_geometry *g, int32_t n_slices, const float *image,
                         float *sino, float alpha, int32_t accumulate, xct_stream stream);
 

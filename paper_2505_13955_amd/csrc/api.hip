@@ -851,6 +851,8 @@ int xct_forward_project(const xct_geometry *g, int32_t n_slices, const float *im
     // four slices per workgroup share coordinates and weights; a call with
     // one or two slices keeps one per workgroup
     const int sl = (n_slices >= 3 && t->rows[1] > 0) ? 4 : 1;
+    // one workgroup per (slice group, bin block, angle block), indexed in 32 bits
+    if ((int64_t)a.n_blocks * a.bin_blocks * ((n_slices + sl - 1) / sl) >= ((int64_t)1 << 31)) return XCT_ETOOBIG;
     a.rows = t->rows[sl == 4];
     a.pitch = t->pitch[sl == 4];
     a.scale = (float)((double)alpha * projector_scale(g));

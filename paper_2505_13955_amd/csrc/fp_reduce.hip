@@ -13,7 +13,10 @@
 // image a few steps at a time: it stages into LDS, with coalesced reads, the
 // rectangle of pixels those strips can touch (zeros outside the image), then
 // every thread adds its taps for its 16 bins, and at the end the results go
-// out through LDS so that the stores run along bins.  Per stage a thread
+// out through LDS so that the stores run along bins.  Each XCD takes a
+// contiguous run of (slice group, bin block, angle block) triples, angle
+// blocks fastest, so that the workgroups sharing an L2 stage overlapping
+// rectangles of the same slices.  Per stage a thread
 // anchors its first bin's crossing in FP64 and keeps an integer index plus an
 // FP32 offset below 16/|A| + the staged rows' count, so the hat weights
 // carry rounding of the order of 2^-18 pixel.  Fixed summation order: the
@@ -77,10 +80,16 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int q = lane & 15;                       // angle of the block
-    const int wg = a.block_base + (int)blockIdx.x;
-    const int blk = wg / a.bin_blocks;
-    const int bb = wg - blk * a.bin_blocks;
-    const int z0 = blockIdx.y * SL;
+    // workgroup i of a launch runs on XCD i mod 8: give each XCD a
+    // contiguous run of (slice group, bin block, angle block) triples, angle
+    // block fastest, so the workgroups of one XCD stage overlapping pixels
+    const int n_wg = (int)gridDim.x, xcd = (int)blockIdx.x & 7, jx = (int)blockIdx.x >> 3;
+    const int qx = n_wg >> 3, rx = n_wg & 7;
+    const int wg = a.block_base + xcd * qx + min(xcd, rx) + jx;
+    const int blk = wg % a.n_blocks;
+    const int tb = wg / a.n_blocks;
+    const int bb = tb % a.bin_blocks;
+    const int z0 = (tb / a.bin_blocks) * SL;
     const int nsl = min(SL, a.n_slices - z0);  // slices present in this group
     const FPBlock B = a.blocks[blk];
     const int walk = B.walk, count = B.count, k0 = B.k0;
@@ -259,15 +268,15 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
 
 hipError_t launch_forward(const FPArgs &a, int sl, hipStream_t s)
 {
-    // x: (angle block, bin block) pairs, split so that no launch exceeds
-    // 2^32 - 1 work-items along x; y: groups of `sl` slices
-    const int64_t total = (int64_t)a.n_blocks * a.bin_blocks;
+    // one workgroup per (slice group, bin block, angle block) triple, split
+    // so that no launch exceeds 2^32 - 1 work-items
+    const int64_t total = (int64_t)a.n_blocks * a.bin_blocks * ((a.n_slices + sl - 1) / sl);
     const int64_t max_x = ((((int64_t)1 << 32) - 1) / kFPBins);
     (void)hipGetLastError();
     FPArgs c = a;
     for (int64_t x0 = 0; x0 < total; x0 += max_x) {
         c.block_base = (int32_t)x0;
-        dim3 grid((unsigned)(total - x0 < max_x ? total - x0 : max_x), (unsigned)((a.n_slices + sl - 1) / sl));
+        dim3 grid((unsigned)(total - x0 < max_x ? total - x0 : max_x));
         if (sl == 4)
             hipLaunchKernelGGL(fp_tile_kernel<4>, grid, dim3(kFPBins), 0, s, c);
         else

@@ -147,7 +147,7 @@ struct FPArgs {
     const FPAngle *ang;  // [Np]
     const FPBlock *blocks;
     int32_t n_blocks, bin_blocks;
-    int32_t block_base;  // (angle block, bin block) index of workgroup x = 0
+    int32_t block_base;  // (slice group, bin block, angle block) index of the launch's first workgroup
     int32_t rows;        // walk steps staged at a time (power of two)
     int32_t pitch;       // LDS floats per staged walk step
     float scale;
