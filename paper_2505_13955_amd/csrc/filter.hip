@@ -758,7 +758,8 @@ __device__ __forceinline__ void load_raw_quads(uint2 (&q)[8], const FilterArgs &
 // N_c = 4 n_q samples from src into dst, by quads: thread T of the row takes
 // quads T + i TN, i < 8.  A quad whose taps stay inside the row reads its
 // neighbour quads as 16-byte words; the quads within R samples of an end
-// read clamped samples one at a time.
+// read clamped samples one at a time.  (Blurs of R <= 4 take a path without
+// the second buffer, in the kernel.)
 template <int TN>
 __device__ __forceinline__ void blur_quads(const float *src, float *dst, int nc, int R, const float *w, int T)
 {
@@ -766,60 +767,31 @@ __device__ __forceinline__ void blur_quads(const float *src, float *dst, int nc,
     const int QR = (R + 3) >> 2;  // neighbour quads each side
     const float4 *s4 = reinterpret_cast<const float4 *>(src);
     float4 *d4 = reinterpret_cast<float4 *>(dst);
-    auto edge = [&](int q) {
-        float o[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        for (int m = -R; m <= R; ++m) {
-            const float wm = w[m + R];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) o[c] = fmaf(wm, src[min(max(4 * q + c + m, 0), nc - 1)], o[c]);
+    for (int i = 0; i < 8; ++i) {
+        const int q = T + i * TN;
+        if (q >= nq) continue;
+        float o[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (q >= QR && q + QR < nq) {
+            for (int j = -QR; j <= QR; ++j) {
+                const float4 u = s4[q + j];
+                const float v[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                for (int cc = 0; cc < 4; ++cc)
+#pragma unroll
+                    for (int cp = 0; cp < 4; ++cp) {
+                        const int m = 4 * j + cp - cc;
+                        if (m >= -R && m <= R) o[cc] = fmaf(w[m + R], v[cp], o[cc]);
+                    }
+            }
+        } else {
+            for (int m = -R; m <= R; ++m) {
+                const float wm = w[m + R];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) o[c] = fmaf(wm, src[min(max(4 * q + c + m, 0), nc - 1)], o[c]);
+            }
         }
         d4[q] = make_float4(o[0], o[1], o[2], o[3]);
-    };
-    if (R <= 4) {
-        // taps padded to w[-4..4]: three quads q - 1, q, q + 1 cover them
-        float tk[9];
-#pragma unroll
-        for (int m = -4; m <= 4; ++m) tk[m + 4] = (m >= -R && m <= R) ? w[min(max(m + R, 0), 2 * R)] : 0.0f;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int q = T + i * TN;
-            if (q >= nq) continue;
-            if (q >= 1 && q + 1 < nq) {
-                const float4 a = s4[q - 1], b = s4[q], c = s4[q + 1];
-                const float v[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
-                float o[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                for (int m = -4; m <= 4; ++m)
-#pragma unroll
-                    for (int cc = 0; cc < 4; ++cc) o[cc] = fmaf(tk[m + 4], v[4 + cc + m], o[cc]);
-                d4[q] = make_float4(o[0], o[1], o[2], o[3]);
-            } else {
-                edge(q);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int q = T + i * TN;
-            if (q >= nq) continue;
-            if (q >= QR && q + QR < nq) {
-                float o[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-                for (int j = -QR; j <= QR; ++j) {
-                    const float4 u = s4[q + j];
-                    const float v[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-                    for (int cc = 0; cc < 4; ++cc)
-#pragma unroll
-                        for (int cp = 0; cp < 4; ++cp) {
-                            const int m = 4 * j + cp - cc;
-                            if (m >= -R && m <= R) o[cc] = fmaf(w[m + R], v[cp], o[cc]);
-                        }
-                }
-                d4[q] = make_float4(o[0], o[1], o[2], o[3]);
-            } else {
-                edge(q);
-            }
-        }
     }
 }
 
@@ -983,22 +955,67 @@ __global__ __launch_bounds__(256) void filter_fused_kernel(FilterArgs a, int in_
 #pragma unroll
             for (int i = 0; i < 32; ++i) x[i] = make_float2(0.0f, 0.0f);
             if constexpr (FEP) {
-                // blurred row into the upper half of the row's region
-                // (N_c <= M floats each), then the elements' sample pairs
-                const float *src = stage;
-                if (R > 0) {
+                const float2 *p2 = reinterpret_cast<const float2 *>(stage);
+                if (R == 0) {
+#pragma unroll
+                    for (int b = 0; b < NB1; ++b)
+#pragma unroll
+                        for (int t = 0; t < H1; ++t) {
+                            const int e = T + b * TN + t * (M / R1);
+                            if (live && 2 * e < nc) x[b * R1 + t] = p2[e];
+                        }
+                } else if (R <= 4) {
+                    // taps padded to w[-4..4]: element e (bins 2e, 2e + 1)
+                    // reads the sample pairs e - 2 .. e + 2 when they lie in
+                    // the row; elements near an end read clamped samples
+                    float tk[9];
+#pragma unroll
+                    for (int m = -4; m <= 4; ++m)
+                        tk[m + 4] = (m >= -R && m <= R) ? pre.taps[min(max(m + R, 0), 2 * R)] : 0.0f;
+#pragma unroll
+                    for (int b = 0; b < NB1; ++b)
+#pragma unroll
+                        for (int t = 0; t < H1; ++t) {
+                            const int e = T + b * TN + t * (M / R1);
+                            if (!live || 2 * e >= nc) continue;
+                            float o0 = 0.0f, o1 = 0.0f;
+                            if (e >= 2 && 2 * e + 5 < nc) {
+                                float sm[10];  // samples 2e - 4 .. 2e + 5
+#pragma unroll
+                                for (int k = 0; k < 5; ++k) {
+                                    const float2 v = p2[e - 2 + k];
+                                    sm[2 * k] = v.x;
+                                    sm[2 * k + 1] = v.y;
+                                }
+#pragma unroll
+                                for (int m = -4; m <= 4; ++m) {
+                                    o0 = fmaf(tk[m + 4], sm[4 + m], o0);
+                                    o1 = fmaf(tk[m + 4], sm[5 + m], o1);
+                                }
+                            } else {
+                                for (int m = -R; m <= R; ++m) {
+                                    const float wm = pre.taps[m + R];
+                                    o0 = fmaf(wm, stage[min(max(2 * e + m, 0), nc - 1)], o0);
+                                    o1 = fmaf(wm, stage[min(max(2 * e + 1 + m, 0), nc - 1)], o1);
+                                }
+                            }
+                            x[b * R1 + t] = make_float2(o0, o1);
+                        }
+                } else {
+                    // wider blurs: the blurred row into the upper half of
+                    // the row's region (N_c <= M floats each), then the
+                    // elements' sample pairs
                     if (live) blur_quads<TN>(stage, stage + M, nc, R, pre.taps, T);
                     __syncthreads();
-                    src = stage + M;
+                    const float2 *b2 = reinterpret_cast<const float2 *>(stage + M);
+#pragma unroll
+                    for (int b = 0; b < NB1; ++b)
+#pragma unroll
+                        for (int t = 0; t < H1; ++t) {
+                            const int e = T + b * TN + t * (M / R1);
+                            if (live && 2 * e < nc) x[b * R1 + t] = b2[e];
+                        }
                 }
-                const float2 *p2 = reinterpret_cast<const float2 *>(src);
-#pragma unroll
-                for (int b = 0; b < NB1; ++b)
-#pragma unroll
-                    for (int t = 0; t < H1; ++t) {
-                        const int e = T + b * TN + t * (M / R1);
-                        if (live && 2 * e < nc) x[b * R1 + t] = p2[e];
-                    }
             } else if (R == 0) {
 #pragma unroll
                 for (int b = 0; b < NB1; ++b)

@@ -204,6 +204,9 @@ FE_CASES = [
     (300, 2, 8192, 0, 2, 1.0, torch.uint16, torch.float32, "hann"),
     (6000, 3, 256, 0, 3, 1.0, torch.uint16, torch.float32, "ram_lak"),
     (4001, 4, 1024, 2, 2, 2.0, torch.uint16, torch.bfloat16, "shepp_logan"),
+    # persistent front end with a three-tap blur (radius 2) and without blur
+    (50, 2, 512, 0, 2, 0.5, torch.uint16, torch.float32, "hann"),
+    (40, 2, 1024, 1, 1, 0.0, torch.uint16, torch.float32, "ram_lak"),
 ]
 
 
