@@ -8,8 +8,8 @@
 // a bin's strip crosses at most floor(2/|A|) + 1 pixels, centred on
 //   v*(n, w) = (n - u0 - B w) / A.
 // A workgroup takes one block of up to 16 consecutive angles that share the
-// walk axis and one block of 256 bins; a thread takes one angle and 16
-// consecutive bins (16 angles x 4 bin groups per wavefront).  It walks the
+// walk axis and one block of 256 bins; a thread takes one angle and 16 bins
+// four apart (16 angles x 4 interleaved bin groups per wavefront).  It walks the
 // image a few steps at a time: it stages into LDS, with coalesced reads, the
 // rectangle of pixels those strips can touch (zeros outside the image), then
 // every thread adds its taps for its 16 bins, and at the end the results go
@@ -18,8 +18,8 @@
 // blocks fastest, so that the workgroups sharing an L2 stage overlapping
 // rectangles of the same slices.  Per stage a thread
 // anchors its first bin's crossing in FP64 and keeps an integer index plus an
-// FP32 offset below 16/|A| + the staged rows' count, so the hat weights
-// carry rounding of the order of 2^-18 pixel.  Fixed summation order: the
+// FP32 offset below 64/|A| + the staged rows' count, so the hat weights
+// carry rounding of the order of 2^-17 pixel.  Fixed summation order: the
 // output is deterministic.
 //
 // Reductions: a fixed grid of workgroups accumulates FP64 partial sums
@@ -59,12 +59,13 @@ template <> struct FPVec<4> {
     }
 };
 
-// Lanes of a wavefront: 16 angles of the block x 4 groups of 16 consecutive
-// bins; a thread accumulates its angle's 16 bins for SL slices.  Lanes that
-// read together are the block's angles at the same bins, whose taps lie a
-// few pixels apart (often at the same address); lanes one bin apart at one
-// angle would read pixels 1/|A| > 1 apart, which costs more LDS bank
-// conflicts.
+// Lanes of a wavefront: 16 angles of the block x 4 bin groups; group g of
+// wavefront v takes bins 64 v + g + 4 b, b < 16, of the block, and a thread
+// accumulates its angle's 16 bins for SL slices.  Lanes that read together
+// are the block's angles at four adjacent bins, whose taps lie within a few
+// pixels of each other (often at the same address).  With groups of 16
+// consecutive bins the four groups' taps sat about 16 pixels (16 entries of
+// 16 bytes) apart, on the same LDS banks, and the kernel ran 8 % slower.
 template <int SL>
 __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
 {
@@ -96,7 +97,7 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
     const int nv = walk ? a.ny : a.nx, nw = walk ? a.nx : a.ny;
     const int n0 = bb * kFPBins;
     const int n1 = n0 + kFPBins - 1;  // the plan sizes stages for whole bin blocks
-    const int nb = n0 + wave * 64 + (lane >> 4) * kBinsPerThread;  // this thread's first bin
+    const int nb = n0 + wave * 64 + (lane >> 4);  // this thread's first bin; its bins are nb + 4 b
     const int64_t plane = (int64_t)a.nx * a.ny;
     const float *img = a.image + (int64_t)z0 * plane;
     const int pitch = a.pitch, rows = a.rows;
@@ -186,15 +187,15 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
         }
         __syncthreads();
 
-        // This thread's crossings: v*(nb + b, w0 + r) - vlo = rel0 + b/A + r dv,
+        // This thread's crossings: v*(nb + 4b, w0 + r) - vlo = rel0 + 4b/A + r dv,
         // anchored once per stage in FP64 (integer part bi0, FP32 fraction f00)
-        // so that the FP32 offsets stay below 16/|A| + rows (~2^-18 pixel).
+        // so that the FP32 offsets stay below 64/|A| + rows (~2^-17 pixel).
         const double rel0 = ((double)nb - p.u0 - p.B * (double)w0) * p.invA - (double)vlo;
         const int bi0 = (int)floor(rel0);
         const float f00 = (float)(rel0 - (double)bi0);
         {
             // skip the stage when no strip of the wavefront reaches the image
-            const float e0 = f00 + (float)bi0, eb = 15.0f * invA, er = (float)(rc - 1) * p.dv;
+            const float e0 = f00 + (float)bi0, eb = 60.0f * invA, er = (float)(rc - 1) * p.dv;
             const float lo = e0 + fminf(eb, 0.0f) + fminf(er, 0.0f);
             const float hi = e0 + fmaxf(eb, 0.0f) + fmaxf(er, 0.0f);
             const bool hits = on && hi + p.hw > (float)(-vlo) - 1.0f && lo - p.hw < (float)(nv - vlo);
@@ -210,7 +211,7 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
                 const VT *row = base + r * pitch;
 #pragma unroll
                 for (int b = 0; b < kBinsPerThread; ++b) {
-                    const float vloc = fmaf((float)b, invA, vr);
+                    const float vloc = fmaf((float)(4 * b), invA, vr);
                     const float vl = ceilf(vloc - p.hw);
                     const float t = vl - vloc;
                     const VT *src = row + (int)vl;
@@ -229,7 +230,7 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
                 const VT *row = base + r * pitch;
 #pragma unroll
                 for (int b = 0; b < kBinsPerThread; ++b) {
-                    const float vloc = fmaf((float)b, invA, vr);
+                    const float vloc = fmaf((float)(4 * b), invA, vr);
                     const float vl = ceilf(vloc - p.hw);
                     const float t = vl - vloc;
                     const VT *src = row + (int)vl;
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
         __syncthreads();
 #pragma unroll
         for (int b = 0; b < kBinsPerThread; ++b)
-            out_lds[q * kOutPitch + (nb - n0) + b] = V::get(acc[b], sl);
+            out_lds[q * kOutPitch + (nb - n0) + 4 * b] = V::get(acc[b], sl);
         __syncthreads();
         const int n = n0 + tid;
         if (n < a.n_det) {
