@@ -7,7 +7,10 @@ exact transpose, the back-projector, as a torch.autograd.Function.
 Slices are processed ``chunk`` at a time so that the launches of one call stay
 bounded; ``ls_loss_and_grad`` goes further and streams the least-squares loss
 ||P x - y||^2 and its gradient 2 P^T (P x - y) slice chunk by slice chunk,
-holding only one chunk's projections at a time.  Loss sums are FP64.
+holding only one chunk's projections at a time.  Loss sums are FP64.  The
+default chunk holds as many slices as keep one chunk's projections within
+CHUNK_BYTES (1 GiB: 128 slices of 1440 x 1449 bins), so a stack that fits
+runs as one launch per operator and larger stacks stream.
 """
 
 from __future__ import annotations
@@ -16,10 +19,18 @@ import torch
 
 from . import xct
 
+CHUNK_BYTES = 1 << 30
+
+
+def default_chunk(geom) -> int:
+    """Slices per chunk whose FP32 projections fit CHUNK_BYTES (at least one)."""
+    return max(1, CHUNK_BYTES // (4 * geom.n_angles * geom.n_det))
+
 
 class XctProject(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, x: torch.Tensor, geom, chunk: int = 16):
+    def forward(ctx, x: torch.Tensor, geom, chunk: int | None = None):
+        chunk = chunk or default_chunk(geom)
         x = x.contiguous()
         ctx.geom = geom
         ctx.chunk = chunk
@@ -40,17 +51,18 @@ class XctProject(torch.autograd.Function):
         return gx, None, None
 
 
-def project(x: torch.Tensor, geom, chunk: int = 16) -> torch.Tensor:
+def project(x: torch.Tensor, geom, chunk: int | None = None) -> torch.Tensor:
     """P x for x of shape (S, N_y, N_x), differentiable in x."""
     return XctProject.apply(x, geom, chunk)
 
 
-def ls_loss_and_grad(x: torch.Tensor, y: torch.Tensor, geom, chunk: int = 16):
+def ls_loss_and_grad(x: torch.Tensor, y: torch.Tensor, geom, chunk: int | None = None):
     """(||P x - y||^2 as a float64 device scalar, 2 P^T (P x - y) as FP32),
     computed chunk by chunk of slices, holding one chunk's residual at a time.
     The residual is formed inside the forward projector, which accumulates
     -P x onto a copy of y (r = y - P x); the loss is an FP64 reduction of r and
     the gradient one back-projection, -2 P^T r."""
+    chunk = chunk or default_chunk(geom)
     x = x.contiguous()
     y = y.contiguous()
     S = x.shape[0]

@@ -259,3 +259,17 @@ def test_no_device_reports_hip_error(lib):
     assert lib.xct_forward_project(ctypes.byref(g), 1, FAKE, FAKE2, 1.0, 0, None) == -5
     assert lib.xct_dot_f64(FAKE, FAKE2, 10, FAKE, ctypes.c_void_p(0x10000), 8, None) == -5
     assert lib.xct_dot_f64_noalloc(FAKE, FAKE2, 10, FAKE, None) == -5
+
+
+def test_default_chunk_holds_a_gigabyte_of_projections():
+    """The projector pair's default slice chunk keeps one chunk's FP32
+    projections within 1 GiB: 128 slices of 1440 x 1449 bins, at least one
+    slice however wide the sinogram."""
+    import types
+
+    from paper_2505_13955_amd.autograd import CHUNK_BYTES, default_chunk
+
+    assert CHUNK_BYTES == 1 << 30
+    assert default_chunk(types.SimpleNamespace(n_angles=1440, n_det=1449)) == 128
+    assert default_chunk(types.SimpleNamespace(n_angles=6144, n_det=8192)) == 5
+    assert default_chunk(types.SimpleNamespace(n_angles=1 << 20, n_det=8192)) == 1

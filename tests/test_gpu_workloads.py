@@ -320,11 +320,13 @@ def test_c4_streamed_loss_and_gradient_against_oracle(xct, c4_problem):
     residual buffer reused six times): the loss against the oracle's
     ||P x - y||^2 over all 32 slices, and the gradient against the oracle's
     on slices 0, 15, 16 and 31, on both sides of the chunk boundaries, and
-    against the autograd pair."""
+    against the autograd pair; and the default chunk (the whole stack in one
+    chunk here)."""
     spec, g, x, y = c4_problem
-    say("c4 streamed gradient, chunks of 16 and 5")
+    say("c4 streamed gradient, chunks of 16 and 5 and the default")
     loss16, grad16 = xct.ls_loss_and_grad(x, y, g, chunk=16)
     loss5, grad5 = xct.ls_loss_and_grad(x, y, g, chunk=5)
+    lossd, gradd = xct.ls_loss_and_grad(x, y, g)
     xr = x.clone().requires_grad_(True)
     ((xct.project(xr, g) - y) ** 2).sum().backward()
     torch.cuda.synchronize()
@@ -343,7 +345,7 @@ def test_c4_streamed_loss_and_gradient_against_oracle(xct, c4_problem):
     # FP32 ray sums round at ~2^-24 |P x|; relative to the residual that is
     # rho = ||P x|| / ||r|| times larger, accumulated over ~sqrt(N) terms
     tol = max(1e-4, 2 * rho * math.sqrt(g.nx) * 2.0 ** -24)
-    for name, loss in (("chunk 16", loss16), ("chunk 5", loss5)):
+    for name, loss in (("chunk 16", loss16), ("chunk 5", loss5), ("default chunk", lossd)):
         el = abs(float(loss) - lref) / lref
         say(f"  loss {name}: rel err {el:.3e}")
         assert el < 1e-5
@@ -351,9 +353,11 @@ def test_c4_streamed_loss_and_gradient_against_oracle(xct, c4_problem):
         gref = 2.0 * oracle.backproject(resid[s], g, oracle.adjoint_scale(g))
         e16 = rel_l2(grad16[s].cpu().numpy(), gref)
         e5 = rel_l2(grad5[s].cpu().numpy(), gref)
+        ed = rel_l2(gradd[s].cpu().numpy(), gref)
         ea = rel_l2(xr.grad[s].cpu().numpy(), gref)
-        say(f"  slice {s}: rho {rho:.1f} tol {tol:.2e}  chunk16 {e16:.3e} chunk5 {e5:.3e} autograd {ea:.3e}")
-        assert e16 < tol and e5 < tol and ea < tol
+        say(f"  slice {s}: rho {rho:.1f} tol {tol:.2e}  chunk16 {e16:.3e} chunk5 {e5:.3e} default {ed:.3e} "
+            f"autograd {ea:.3e}")
+        assert e16 < tol and e5 < tol and ed < tol and ea < tol
     # chunking changes no slice's arithmetic beyond the forward projector's
     # variant for a 1- or 2-slice chunk: equal within the oracle gate
     assert rel_l2(grad5.cpu().numpy(), grad16.cpu().numpy()) < tol
