@@ -205,23 +205,33 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
         if (three) {
             // taps at t <= 0, t + 1 (|t + 1| |A| <= 1) and t + 2 > 0 pixels
             // from the crossing: the first and last weights need no absolute
-            // value, the middle one no clamp
+            // value, the middle one no clamp, and the first none either
+            // (t >= -1/|A|, so 1 + |A| t >= 0 up to rounding)
             for (int r = 0; r < rc; ++r) {
                 const float vr = fmaf((float)r, p.dv, f00);
                 const VT *row = base + r * pitch;
-#pragma unroll
-                for (int b = 0; b < kBinsPerThread; ++b) {
+                // the taps of bin b + 1 are read before bin b's are added
+                VT x[2][3];
+                float w[2][3];
+                auto fetch = [&](int b, VT (&xx)[3], float (&ww)[3]) {
                     const float vloc = fmaf((float)(4 * b), invA, vr);
                     const float vl = ceilf(vloc - p.hw);
                     const float t = vl - vloc;
                     const VT *src = row + (int)vl;
-                    const VT x0 = src[0], x1 = src[1], x2 = src[2];
-                    const float w0 = fmaxf(fmaf(p.absA, t, 1.0f), 0.0f);
-                    const float w1 = fmaf(-p.absA, fabsf(t + 1.0f), 1.0f);
-                    const float w2 = fmaxf(fmaf(-p.absA, t, c2), 0.0f);
-                    acc[b] = V::fma(w0, x0, acc[b]);
-                    acc[b] = V::fma(w1, x1, acc[b]);
-                    acc[b] = V::fma(w2, x2, acc[b]);
+                    xx[0] = src[0];
+                    xx[1] = src[1];
+                    xx[2] = src[2];
+                    ww[0] = fmaf(p.absA, t, 1.0f);
+                    ww[1] = fmaf(-p.absA, fabsf(t + 1.0f), 1.0f);
+                    ww[2] = fmaxf(fmaf(-p.absA, t, c2), 0.0f);
+                };
+                fetch(0, x[0], w[0]);
+#pragma unroll
+                for (int b = 0; b < kBinsPerThread; ++b) {
+                    if (b + 1 < kBinsPerThread) fetch(b + 1, x[(b + 1) & 1], w[(b + 1) & 1]);
+                    acc[b] = V::fma(w[b & 1][0], x[b & 1][0], acc[b]);
+                    acc[b] = V::fma(w[b & 1][1], x[b & 1][1], acc[b]);
+                    acc[b] = V::fma(w[b & 1][2], x[b & 1][2], acc[b]);
                 }
             }
         } else {
