@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
     const FPAngle p = a.ang[k0 + (on ? q : 0)];
     const float invA = (float)p.invA;
     const bool three = p.taps <= 3 && p.absA <= 1.0f;  // hat two to three pixels wide
-    const float c2 = fmaf(-2.0f, p.absA, 1.0f);
+    const float c1 = 1.0f - p.hw, c3 = fmaf(-2.0f, p.absA, 2.0f);
 
     VT acc[kBinsPerThread];
 #pragma unroll
@@ -203,27 +203,28 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
         }
         const VT *base = tile + bi0;
         if (three) {
-            // taps at t <= 0, t + 1 (|t + 1| |A| <= 1) and t + 2 > 0 pixels
-            // from the crossing: the first and last weights need no absolute
-            // value, the middle one no clamp, and the first none either
-            // (t >= -1/|A|, so 1 + |A| t >= 0 up to rounding)
+            // taps at the first pixel inside the hat's left edge e =
+            // crossing - 1/|A| and the next two; with s = ceil(e) - e in
+            // [0, 1) the weights 1 - |A| |pixel - crossing| are |A| s,
+            // 1 - |A| |s + 1 - 1/|A||, and max(2 - 2|A| - |A| s, 0) (the
+            // first never negative, the middle one never clamped)
             for (int r = 0; r < rc; ++r) {
-                const float vr = fmaf((float)r, p.dv, f00);
+                const float er = fmaf((float)r, p.dv, f00) - p.hw;
                 const VT *row = base + r * pitch;
                 // the taps of bin b + 1 are read before bin b's are added
                 VT x[2][3];
                 float w[2][3];
                 auto fetch = [&](int b, VT (&xx)[3], float (&ww)[3]) {
-                    const float vloc = fmaf((float)(4 * b), invA, vr);
-                    const float vl = ceilf(vloc - p.hw);
-                    const float t = vl - vloc;
+                    const float e = fmaf((float)(4 * b), invA, er);
+                    const float vl = ceilf(e);
+                    const float sd = vl - e;
                     const VT *src = row + (int)vl;
                     xx[0] = src[0];
                     xx[1] = src[1];
                     xx[2] = src[2];
-                    ww[0] = fmaf(p.absA, t, 1.0f);
-                    ww[1] = fmaf(-p.absA, fabsf(t + 1.0f), 1.0f);
-                    ww[2] = fmaxf(fmaf(-p.absA, t, c2), 0.0f);
+                    ww[0] = p.absA * sd;
+                    ww[1] = fmaf(-p.absA, fabsf(sd + c1), 1.0f);
+                    ww[2] = fmaxf(fmaf(-p.absA, sd, c3), 0.0f);
                 };
                 fetch(0, x[0], w[0]);
 #pragma unroll
