@@ -8,8 +8,9 @@
 // kernel computes it as IFFT_L(FFT_L(x) H) with H = DFT_L(h_W) precomputed on
 // the host in FP64 (real and even, since h_W is symmetric).
 //
-// One workgroup filters one row.  The real row x of length L = 2M is packed as
-// z[n] = x[2n] + i x[2n+1] and transformed with one complex FFT of length M;
+// Each row is filtered inside one workgroup.  The real row x of length
+// L = 2M is packed as z[n] = x[2n] + i x[2n+1] and transformed with one
+// complex FFT of length M;
 // a single pass over the bin pairs (k, M - k) recovers the real row's spectrum
 //   X[k] = E + W^k O,  X[M-k] = conj(E - W^k O),  W = exp(-2 pi i / L),
 //   E = (Z[k] + conj Z[M-k]) / 2,  O = (Z[k] - conj Z[M-k]) / 2i,
