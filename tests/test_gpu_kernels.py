@@ -241,6 +241,54 @@ def test_preprocess_filter_matches_oracle(xct, case):
     assert err < tol, err
 
 
+def test_preprocess_filter_persistent_and_fallback_forms_agree(xct):
+    """uint16 counts over N_c = 1024 take the persistent front end when the
+    stack is 8-byte and the fields 16-byte aligned; the same data through
+    fields one float off that alignment, and through a stack one count off
+    it, take the one-row-per-workgroup form.  All three against the oracle,
+    and the two forms within the FP32 gate of each other."""
+    from oracle import pipeline as pl
+
+    n_p, n_r, n_c, r0, S, sigma = 700, 3, 1024, 1, 2, 1.0
+    rng = np.random.default_rng(77)
+    g = _geom(n_angles=n_p, n_det=n_c, nx=8, ny=8, det_pitch=1.0)
+    dark, flat = synth.detector_fields(n_r, n_c, 77)
+    lines = torch.as_tensor(rng.uniform(0.0, 3.0, (n_r, n_p, n_c)))
+    proj = synth.raw_counts(lines, dark, flat, 1.0, dtype=torch.uint16)
+    counts = proj.numpy().astype(np.float64)
+    p = pl.preprocess(counts, dark.numpy(), flat.numpy(), r0, S, 1.0, sigma)
+    ref = oracle.filter(p, g.det_pitch, "hann")
+
+    def run(proj_dev, dark_dev, flat_dev):
+        out = torch.empty((S, n_p, n_c), dtype=torch.float32, device="cuda")
+        xct.xct_preprocess_filter(g, proj_dev, dark_dev, flat_dev, r0, out, "hann", 1.0, sigma)
+        torch.cuda.synchronize()
+        return out.cpu().numpy()
+
+    say("front end: persistent form and fallbacks")
+    p16 = proj.view(torch.int16).cuda().view(torch.uint16)
+    aligned = run(p16, dark.cuda(), flat.cuda())
+    # fields one float past a 16-byte boundary
+    dbuf = torch.empty(dark.numel() + 1, device="cuda")
+    fbuf = torch.empty(flat.numel() + 1, device="cuda")
+    d1 = dbuf[1:].view(n_r, n_c)
+    f1 = fbuf[1:].view(n_r, n_c)
+    d1.copy_(dark.cuda())
+    f1.copy_(flat.cuda())
+    shifted_fields = run(p16, d1, f1)
+    # stack one count past an 8-byte boundary
+    sbuf = torch.empty(proj.numel() + 1, dtype=torch.int16, device="cuda")
+    s1 = sbuf[1:].view(proj.shape)
+    s1.copy_(proj.view(torch.int16).cuda())
+    shifted_stack = run(s1.view(torch.uint16), dark.cuda(), flat.cuda())
+    for name, got in (("aligned", aligned), ("fields off", shifted_fields), ("stack off", shifted_stack)):
+        err = rel_l2(got, ref)
+        say(f"  {name}: rel L2 {err:.3e}")
+        assert err < 2e-5, (name, err)
+    assert rel_l2(shifted_fields, aligned.astype(np.float64)) < 2e-5
+    assert np.array_equal(shifted_fields, shifted_stack)
+
+
 def test_preprocess_filter_without_blur_equals_filter_of_line_integrals(xct):
     """sigma = 0 and FP32 line integrals given as counts of a unit flat field and
     zero dark current (I = exp(-p)): the front end reduces to xct_filter of p,
