@@ -504,7 +504,7 @@ FP_CASES = [
 
 
 @pytest.mark.parametrize("case", range(len(FP_CASES)))
-@pytest.mark.parametrize("n_slices", [2, 5])
+@pytest.mark.parametrize("n_slices", [2, 5, 8, 16])
 def test_forward_matches_oracle(xct, case, n_slices):
     rng = np.random.default_rng(200 + case)
     c = dict(FP_CASES[case])
@@ -514,7 +514,8 @@ def test_forward_matches_oracle(xct, case, n_slices):
     else:
         c["angles"] = synth.uniform_angles(c["n_angles"])
     g = _geom(**c)
-    # two slices: one per workgroup; five: four per workgroup and a partial group
+    # two slices: one per workgroup; five: four per workgroup and a partial
+    # group; eight and sixteen: full groups of four
     x = rng.standard_normal((n_slices, g.ny, g.nx))
     say("fp", case, n_slices)
     y = xct.forward_project(to_dev(x), g)
