@@ -142,9 +142,11 @@ int xct_filter_offset(const xct_geometry *g, int32_t n_slices, const void *sino,
  * the projection stack as acquired into one sinogram per detector row:
  *   p[s][k][n]  = -ln(max(I - D, floor) / max(F - D, floor)),
  *                 I = proj[k][row_begin + s][n], D = dark[row_begin + s][n],
- *                 F = flat[row_begin + s][n]                      (FP32 logf;
- *                 the quotient by the hardware reciprocal of F - D, taken
- *                 at most 2^126)
+ *                 F = flat[row_begin + s][n]                      (FP32: the
+ *                 quotient by the hardware reciprocal of F - D, taken at
+ *                 most 2^126; the logarithm by the hardware base-2
+ *                 logarithm of the quotient, taken at least 2^-126, so
+ *                 p <= 126 ln 2 = 87.3)
  *   b[s][k][n]  = sum_{|m| <= R} g[m] p[s][k][clamp(n + m, 0, N_c - 1)],
  *                 g[m] = exp(-m^2 / (2 sigma^2)) / sum, R = int(4 sigma + 0.5)
  *                 (sigma = 0: b = p)

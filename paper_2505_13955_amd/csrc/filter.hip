@@ -282,10 +282,13 @@ __device__ __forceinline__ void fft_forward(float2 *z, int L, int log2L, const f
 // Line integral of one raw detector sample (Beer-Lambert, Section V-A c
 // stage 2): -ln((I - D) / (F - D)), both differences clamped below at `floor`.
 // The quotient takes the hardware reciprocal (about one ulp) of F - D, which
-// floor >= the smallest normal float and the cap at 2^126 keep normal.
+// floor >= the smallest normal float and the cap at 2^126 keep normal; the
+// logarithm is the hardware base-2 logarithm of the quotient taken at least
+// 2^-126 (normal), so p <= 126 ln 2 = 87.3 (a transmission of 1e-38).
 __device__ __forceinline__ float beer_lambert(float i, float d, float f, float floor)
 {
-    return -logf(fmaxf(i - d, floor) * __builtin_amdgcn_rcpf(fminf(fmaxf(f - d, floor), 0x1p126f)));
+    const float ratio = fmaxf(i - d, floor) * __builtin_amdgcn_rcpf(fminf(fmaxf(f - d, floor), 0x1p126f));
+    return -0.69314718056f * __builtin_amdgcn_logf(fmaxf(ratio, 0x1p-126f));
 }
 
 // Front end of one row: row r of the output is detector row row_begin + s of
