@@ -87,7 +87,7 @@ struct Entry {
     size_t off[2] = {0, 0};     // offsets of the entry's tables in `dev`
     // forward-projector plan metadata
     int n_blocks = 0;
-    int rows[2] = {0, 0}, pitch[2] = {0, 0};
+    bool fp_four = false;  // every angle block has a four-slice staging shape
     // filter length
     int L = 0, lg = 0;
     template <typename T>
@@ -342,10 +342,9 @@ int fp_tables(const xct_geometry *g, hipStream_t stream, EntryRef *out)
     std::vector<FPAngle> ang;
     std::vector<FPBlock> blocks;
     Entry meta;
-    if (int rc = fp_plan(g, ang, blocks, 1, &meta.rows[0], &meta.pitch[0])) return rc;
     // four slices per workgroup when their staging fits (not for strips many
     // pixels wide)
-    if (fp_plan(g, ang, blocks, 4, &meta.rows[1], &meta.pitch[1]) != XCT_OK) meta.rows[1] = 0;
+    if (int rc = fp_plan(g, ang, blocks, &meta.fp_four)) return rc;
     meta.n_blocks = (int)blocks.size();
     const void *parts[2] = {ang.data(), blocks.data()};
     const size_t sizes[2] = {sizeof(FPAngle) * ang.size(), sizeof(FPBlock) * blocks.size()};
@@ -850,11 +849,9 @@ int xct_forward_project(const xct_geometry *g, int32_t n_slices, const float *im
     a.bin_blocks = (g->n_det + kFPBins - 1) / kFPBins;
     // four slices per workgroup share coordinates and weights; a call with
     // one or two slices keeps one per workgroup
-    const int sl = (n_slices >= 3 && t->rows[1] > 0) ? 4 : 1;
+    const int sl = (n_slices >= 3 && t->fp_four) ? 4 : 1;
     // one workgroup per (slice group, bin block, angle block), indexed in 32 bits
     if ((int64_t)a.n_blocks * a.bin_blocks * ((n_slices + sl - 1) / sl) >= ((int64_t)1 << 31)) return XCT_ETOOBIG;
-    a.rows = t->rows[sl == 4];
-    a.pitch = t->pitch[sl == 4];
     a.scale = (float)((double)alpha * projector_scale(g));
     a.accumulate = accumulate ? 1 : 0;
     a.n_angles = g->n_angles;

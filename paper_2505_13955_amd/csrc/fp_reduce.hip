@@ -100,8 +100,7 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
     const int nb = n0 + wave * 64 + (lane >> 4);  // this thread's first bin; its bins are nb + 4 b
     const int64_t plane = (int64_t)a.nx * a.ny;
     const float *img = a.image + (int64_t)z0 * plane;
-    const int pitch = a.pitch, rows = a.rows;
-    const int lg_rows = __builtin_ctz(rows);
+    const int rows = B.rows[SL == 4 ? 1 : 0], pitch = B.pitch[SL == 4 ? 1 : 0];
     const bool on = q < count;
     const FPAngle p = a.ang[k0 + (on ? q : 0)];
     const float invA = (float)p.invA;
@@ -149,10 +148,13 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
         // `rows` consecutive columns of one image row are read together.
         // (f + 1/2) / width in FP32 recovers the staged row of pixel f
         // exactly: the quotient is below 16, its rounding error below 2^-19,
-        // and its distance to an integer at least 1/(2 width) >= 2^-14.
+        // and its distance to an integer at least 1/(2 width) >= 2^-14; and
+        // (f + 1/2) / rows its column: the quotient is below 2^13, its
+        // rounding error below 2^-10, its distance to an integer at least
+        // 1/(2 rows) >= 2^-5.
         {
             const int total = walk ? width * rows : width * rc;
-            const float invw = 1.0f / (float)width;
+            const float invw = 1.0f / (float)width, invr = 1.0f / (float)rows;
             for (int fb = 0; fb < total; fb += kStageBatch * kFPBins) {
                 VT val[kStageBatch];
                 int dst[kStageBatch];
@@ -164,8 +166,8 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
                         r = (int)(((float)f + 0.5f) * invw);
                         c = f - r * width;
                     } else {
-                        r = f & (rows - 1);
-                        c = f >> lg_rows;
+                        c = (int)(((float)f + 0.5f) * invr);
+                        r = f - c * rows;
                     }
                     const int v = vlo + c;
                     float x[SL];
@@ -326,8 +328,7 @@ int stage_width(const std::vector<FPAngle> &ang, const FPBlock &b, int n0, int w
 
 }  // namespace
 
-int fp_plan(const xct_geometry *g, std::vector<FPAngle> &ang, std::vector<FPBlock> &blocks, int sl,
-            int *rows_out, int *pitch_out)
+int fp_plan(const xct_geometry *g, std::vector<FPAngle> &ang, std::vector<FPBlock> &blocks, bool *four)
 {
     const double r = g->pixel_size / g->det_pitch;
     const double cx = 0.5 * (g->nx - 1), cy = 0.5 * (g->ny - 1);
@@ -368,30 +369,39 @@ int fp_plan(const xct_geometry *g, std::vector<FPAngle> &ang, std::vector<FPBloc
             if (spread > kFPSpread) break;
             ++cnt;
         }
-        blocks.push_back(FPBlock{k, cnt, walk[k], 0});
+        blocks.push_back(FPBlock{k, cnt, walk[k], 0, {0, 0}, {0, 0}});
         k += cnt;
     }
-    // staging shape: the widest stage of any block fits kFPLdsFloats.  The
-    // width is convex in the stage origin (n0, w0), so its maximum over the
-    // launch sits at the extreme origins.
+    // staging shape of each block, for one and for four slices per
+    // workgroup: the most walk steps (at most 16) whose widest stage fits
+    // kFPLdsFloats.  The width is convex in the stage origin (n0, w0), so its
+    // maximum over the launch sits at the extreme origins.  Blocks near an
+    // axis stage more steps at a time than diagonal ones, whose strips cross
+    // wider rectangles.
     const int last_bin_block = ((nc - 1) / kFPBins) * kFPBins;
-    for (int rows = 16; rows >= 1; rows >>= 1) {
-        int need = 0;
-        for (const FPBlock &b : blocks) {
-            const int nw = b.walk ? g->nx : g->ny;
-            const int last_w0 = ((nw - 1) / rows) * rows;
-            for (int c = 0; c < 4; ++c)
-                need = std::max(need, stage_width(ang, b, (c & 1) ? last_bin_block : 0,
-                                                  (c & 2) ? last_w0 : 0, rows));
+    *four = true;
+    for (FPBlock &b : blocks) {
+        const int nw = b.walk ? g->nx : g->ny;
+        for (int f = 0; f < 2; ++f) {
+            const int sl = f ? 4 : 1;
+            for (int rows = 16; rows >= 1; --rows) {
+                const int last_w0 = ((nw - 1) / rows) * rows;
+                int need = 0;
+                for (int c = 0; c < 4; ++c)
+                    need = std::max(need, stage_width(ang, b, (c & 1) ? last_bin_block : 0,
+                                                      (c & 2) ? last_w0 : 0, rows));
+                const int pitch = need | 1;  // odd: column-walk staging writes hit distinct banks
+                if ((int64_t)pitch * rows * sl <= kFPLdsFloats) {
+                    b.rows[f] = rows;
+                    b.pitch[f] = pitch;
+                    break;
+                }
+            }
         }
-        const int pitch = need | 1;  // odd: column-walk staging writes hit distinct banks
-        if ((int64_t)pitch * rows * sl <= kFPLdsFloats) {
-            *rows_out = rows;
-            *pitch_out = pitch;
-            return XCT_OK;
-        }
+        if (b.rows[0] == 0) return XCT_ETOOBIG;
+        if (b.rows[1] == 0) *four = false;
     }
-    return XCT_ETOOBIG;
+    return XCT_OK;
 }
 
 // ---------------------------------------------------------------- reductions

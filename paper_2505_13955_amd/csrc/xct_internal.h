@@ -131,9 +131,12 @@ struct FPAngle {
     int32_t taps;    // floor(2 hw) + 1 taps cover the hat
 };
 // A run of consecutive angles with the same walk axis whose strips stay close
-// together, projected by one workgroup per bin block.
+// together, projected by one workgroup per bin block, and its staging shape
+// for one ([0]) and four ([1]) slices per workgroup: walk steps staged at a
+// time and LDS entries per staged step.
 struct FPBlock {
     int32_t k0, count, walk, pad;
+    int32_t rows[2], pitch[2];
 };
 constexpr int kFPAngles = 16;       // angles per block
 constexpr int kFPBins = 256;        // bins per workgroup (one per thread)
@@ -148,16 +151,14 @@ struct FPArgs {
     const FPBlock *blocks;
     int32_t n_blocks, bin_blocks;
     int32_t block_base;  // (slice group, bin block, angle block) index of the launch's first workgroup
-    int32_t rows;        // walk steps staged at a time (power of two)
-    int32_t pitch;       // LDS floats per staged walk step
     float scale;
     int32_t accumulate;
     int32_t n_angles, n_det, nx, ny, n_slices;
 };
-// Host: angle table, blocks and the LDS shape for `sl` slices per workgroup
-// (XCT_ETOOBIG when no staging shape fits).
-int fp_plan(const xct_geometry *g, std::vector<FPAngle> &ang, std::vector<FPBlock> &blocks, int sl,
-            int *rows, int *pitch);
+// Host: angle table and blocks with their staging shapes (XCT_ETOOBIG when
+// some block has no one-slice shape; *four tells whether every block has a
+// four-slice shape).
+int fp_plan(const xct_geometry *g, std::vector<FPAngle> &ang, std::vector<FPBlock> &blocks, bool *four);
 // `sl`: slices per workgroup, 1 or 4.
 hipError_t launch_forward(const FPArgs &a, int sl, hipStream_t s);
 
