@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
     static_assert(kFPAngles == 16 && kFPBins == 256, "lane layout: 16 angles x 4 bin groups x 4 wavefronts");
     static_assert(kFPAngles * kOutPitch <= kFPLdsFloats, "output transpose fits the staging buffer");
     __shared__ VT tile[kFPLdsFloats / SL];
-    __shared__ int2 range;  // (first staged cross index, staged width)
+    __shared__ int2 range[2];  // per stage (first staged cross index, staged width), two in turn
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int q = lane & 15;                       // angle of the block
@@ -111,12 +111,12 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
 #pragma unroll
     for (int b = 0; b < kBinsPerThread; ++b) acc[b] = V::zero();
 
-    for (int w0 = 0; w0 < nw; w0 += rows) {
-        const int rc = min(rows, nw - w0);
-        __syncthreads();  // the previous stage's readers are done with tile and range
+    // Cross range of the block's strips over the stage at w0, formed by
+    // wavefront 0 into one of two slots: v* is linear in (n, w), so its
+    // extremes sit at the corners.
+    auto plan_range = [&](int w0, int slot) {
         if (tid < 64) {
-            // cross range of the block's strips over this stage: v* is linear
-            // in (n, w), so its extremes sit at the corners
+            const int rc = min(rows, nw - w0);
             double lo = 1e300, hi = -1e300;
             if (tid < 4 * count) {
                 const FPAngle pc = a.ang[k0 + (tid >> 2)];
@@ -135,125 +135,139 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
             if (tid == 0) {
                 const int vlo = (int)floor(lo) - 1;
                 const int vhi = (int)ceil(hi) + 1;
-                range = make_int2(vlo, min(vhi - vlo + 2, pitch));
+                range[slot] = make_int2(vlo, min(vhi - vlo + 2, pitch));
             }
         }
-        __syncthreads();
-        const int vlo = range.x, width = range.y;
-        if (vlo + width <= 0 || vlo >= nv) continue;  // strips miss the image here
+    };
 
-        // Stage walk steps w0 .. w0+rc-1, cross indices vlo .. vlo+width-1,
-        // as a flat range of pixels, several in flight per thread.  Walking
-        // rows, consecutive pixels run along an image row; walking columns,
-        // `rows` consecutive columns of one image row are read together.
-        // (f + 1/2) / width in FP32 recovers the staged row of pixel f
-        // exactly: the quotient is below 16, its rounding error below 2^-19,
-        // and its distance to an integer at least 1/(2 width) >= 2^-14; and
-        // (f + 1/2) / rows its column: the quotient is below 2^13, its
-        // rounding error below 2^-10, its distance to an integer at least
-        // 1/(2 rows) >= 2^-5.
-        {
-            const int total = walk ? width * rows : width * rc;
-            const float invw = 1.0f / (float)width, invr = 1.0f / (float)rows;
-            for (int fb = 0; fb < total; fb += kStageBatch * kFPBins) {
-                VT val[kStageBatch];
-                int dst[kStageBatch];
+    // Stages in turn: the next stage's cross range is formed while the
+    // current stage's readers finish, so a stage takes two barriers.
+    plan_range(0, 0);
+    __syncthreads();
+    for (int s = 0, w0 = 0; w0 < nw; ++s, w0 += rows) {
+        const int rc = min(rows, nw - w0);
+        const int vlo = range[s & 1].x, width = range[s & 1].y;
+        const bool stage_on = vlo + width > 0 && vlo < nv;  // the strips reach the image here
+        if (stage_on) {
+            // Stage walk steps w0 .. w0+rc-1, cross indices vlo .. vlo+width-1,
+            // as a flat range of pixels, several in flight per thread.  Walking
+            // rows, consecutive pixels run along an image row; walking columns,
+            // `rows` consecutive columns of one image row are read together.
+            // (f + 1/2) / width in FP32 recovers the staged row of pixel f
+            // exactly: the quotient is below 16, its rounding error below 2^-19,
+            // and its distance to an integer at least 1/(2 width) >= 2^-14; and
+            // (f + 1/2) / rows its column: the quotient is below 2^13, its
+            // rounding error below 2^-10, its distance to an integer at least
+            // 1/(2 rows) >= 2^-5.
+            {
+                const int total = walk ? width * rows : width * rc;
+                const float invw = 1.0f / (float)width, invr = 1.0f / (float)rows;
+                for (int fb = 0; fb < total; fb += kStageBatch * kFPBins) {
+                    VT val[kStageBatch];
+                    int dst[kStageBatch];
 #pragma unroll
-                for (int i = 0; i < kStageBatch; ++i) {
-                    const int f = fb + i * kFPBins + tid;
-                    int r, c;
-                    if (walk == 0) {
-                        r = (int)(((float)f + 0.5f) * invw);
-                        c = f - r * width;
-                    } else {
-                        c = (int)(((float)f + 0.5f) * invr);
-                        r = f - c * rows;
+                    for (int i = 0; i < kStageBatch; ++i) {
+                        const int f = fb + i * kFPBins + tid;
+                        int r, c;
+                        if (walk == 0) {
+                            r = (int)(((float)f + 0.5f) * invw);
+                            c = f - r * width;
+                        } else {
+                            c = (int)(((float)f + 0.5f) * invr);
+                            r = f - c * rows;
+                        }
+                        const int v = vlo + c;
+                        float x[SL];
+#pragma unroll
+                        for (int sl = 0; sl < SL; ++sl) x[sl] = 0.0f;
+                        if (f < total && r < rc && v >= 0 && v < nv) {
+                            const int64_t off = walk ? (int64_t)v * a.nx + w0 + r : (int64_t)(w0 + r) * a.nx + v;
+#pragma unroll
+                            for (int sl = 0; sl < SL; ++sl)
+                                if (sl < nsl) x[sl] = img[sl * plane + off];
+                        }
+                        val[i] = V::pack(x);
+                        dst[i] = f < total ? r * pitch + c : -1;
                     }
-                    const int v = vlo + c;
-                    float x[SL];
 #pragma unroll
-                    for (int sl = 0; sl < SL; ++sl) x[sl] = 0.0f;
-                    if (f < total && r < rc && v >= 0 && v < nv) {
-                        const int64_t off = walk ? (int64_t)v * a.nx + w0 + r : (int64_t)(w0 + r) * a.nx + v;
-#pragma unroll
-                        for (int sl = 0; sl < SL; ++sl)
-                            if (sl < nsl) x[sl] = img[sl * plane + off];
-                    }
-                    val[i] = V::pack(x);
-                    dst[i] = f < total ? r * pitch + c : -1;
-                }
-#pragma unroll
-                for (int i = 0; i < kStageBatch; ++i)
-                    if (dst[i] >= 0) tile[dst[i]] = val[i];
-            }
-        }
-        __syncthreads();
-
-        // This thread's crossings: v*(nb + 4b, w0 + r) - vlo = rel0 + 4b/A + r dv,
-        // anchored once per stage in FP64 (integer part bi0, FP32 fraction f00)
-        // so that the FP32 offsets stay below 64/|A| + rows (~2^-17 pixel).
-        const double rel0 = ((double)nb - p.u0 - p.B * (double)w0) * p.invA - (double)vlo;
-        const int bi0 = (int)floor(rel0);
-        const float f00 = (float)(rel0 - (double)bi0);
-        {
-            // skip the stage when no strip of the wavefront reaches the image
-            const float e0 = f00 + (float)bi0, eb = 60.0f * invA, er = (float)(rc - 1) * p.dv;
-            const float lo = e0 + fminf(eb, 0.0f) + fminf(er, 0.0f);
-            const float hi = e0 + fmaxf(eb, 0.0f) + fmaxf(er, 0.0f);
-            const bool hits = on && hi + p.hw > (float)(-vlo) - 1.0f && lo - p.hw < (float)(nv - vlo);
-            if (__builtin_amdgcn_ballot_w64(hits) == 0) continue;
-        }
-        const VT *base = tile + bi0;
-        if (three) {
-            // taps at the first pixel inside the hat's left edge e =
-            // crossing - 1/|A| and the next two; with s = ceil(e) - e in
-            // [0, 1) the weights 1 - |A| |pixel - crossing| are |A| s,
-            // 1 - |A| |s + 1 - 1/|A||, and max(2 - 2|A| - |A| s, 0) (the
-            // first never negative, the middle one never clamped)
-            for (int r = 0; r < rc; ++r) {
-                const float er = fmaf((float)r, p.dv, f00) - p.hw;
-                const VT *row = base + r * pitch;
-                // the taps of bin b + 1 are read before bin b's are added
-                VT x[2][3];
-                float w[2][3];
-                auto fetch = [&](int b, VT (&xx)[3], float (&ww)[3]) {
-                    const float e = fmaf((float)(4 * b), invA, er);
-                    const float vl = ceilf(e);
-                    const float sd = vl - e;
-                    const VT *src = row + (int)vl;
-                    xx[0] = src[0];
-                    xx[1] = src[1];
-                    xx[2] = src[2];
-                    ww[0] = p.absA * sd;
-                    ww[1] = fmaf(-p.absA, fabsf(sd + c1), 1.0f);
-                    ww[2] = fmaxf(fmaf(-p.absA, sd, c3), 0.0f);
-                };
-                fetch(0, x[0], w[0]);
-#pragma unroll
-                for (int b = 0; b < kBinsPerThread; ++b) {
-                    if (b + 1 < kBinsPerThread) fetch(b + 1, x[(b + 1) & 1], w[(b + 1) & 1]);
-                    acc[b] = V::fma(w[b & 1][0], x[b & 1][0], acc[b]);
-                    acc[b] = V::fma(w[b & 1][1], x[b & 1][1], acc[b]);
-                    acc[b] = V::fma(w[b & 1][2], x[b & 1][2], acc[b]);
-                }
-            }
-        } else {
-            for (int r = 0; r < rc; ++r) {
-                const float vr = fmaf((float)r, p.dv, f00);
-                const VT *row = base + r * pitch;
-#pragma unroll
-                for (int b = 0; b < kBinsPerThread; ++b) {
-                    const float vloc = fmaf((float)(4 * b), invA, vr);
-                    const float vl = ceilf(vloc - p.hw);
-                    const float t = vl - vloc;
-                    const VT *src = row + (int)vl;
-                    for (int m = 0; m < p.taps; ++m) {
-                        const float wgt = fmaxf(fmaf(-p.absA, fabsf(t + (float)m), 1.0f), 0.0f);
-                        acc[b] = V::fma(wgt, src[m], acc[b]);
-                    }
+                    for (int i = 0; i < kStageBatch; ++i)
+                        if (dst[i] >= 0) tile[dst[i]] = val[i];
                 }
             }
         }
+        __syncthreads();  // the stage is in tile
+        if (stage_on) {
+            // This thread's crossings: v*(nb + 4b, w0 + r) - vlo = rel0 + 4b/A + r dv,
+            // anchored once per stage in FP64 (integer part bi0, FP32 fraction f00)
+            // so that the FP32 offsets stay below 64/|A| + rows (~2^-17 pixel).
+            const double rel0 = ((double)nb - p.u0 - p.B * (double)w0) * p.invA - (double)vlo;
+            const int bi0 = (int)floor(rel0);
+            const float f00 = (float)(rel0 - (double)bi0);
+            bool any_hit;
+            {
+                // skip the stage when no strip of the wavefront reaches the image
+                const float e0 = f00 + (float)bi0, eb = 60.0f * invA, er = (float)(rc - 1) * p.dv;
+                const float lo = e0 + fminf(eb, 0.0f) + fminf(er, 0.0f);
+                const float hi = e0 + fmaxf(eb, 0.0f) + fmaxf(er, 0.0f);
+                const bool hits = on && hi + p.hw > (float)(-vlo) - 1.0f && lo - p.hw < (float)(nv - vlo);
+                any_hit = __builtin_amdgcn_ballot_w64(hits) != 0;
+            }
+            if (any_hit) {
+                const VT *base = tile + bi0;
+                if (three) {
+                    // taps at the first pixel inside the hat's left edge e =
+                    // crossing - 1/|A| and the next two; with s = ceil(e) - e in
+                    // [0, 1) the weights 1 - |A| |pixel - crossing| are |A| s,
+                    // 1 - |A| |s + 1 - 1/|A||, and max(2 - 2|A| - |A| s, 0) (the
+                    // first never negative, the middle one never clamped)
+                    for (int r = 0; r < rc; ++r) {
+                        const float er = fmaf((float)r, p.dv, f00) - p.hw;
+                        const VT *row = base + r * pitch;
+                        // the taps of bin b + 1 are read before bin b's are added
+                        VT x[2][3];
+                        float w[2][3];
+                        auto fetch = [&](int b, VT (&xx)[3], float (&ww)[3]) {
+                            const float e = fmaf((float)(4 * b), invA, er);
+                            const float vl = ceilf(e);
+                            const float sd = vl - e;
+                            const VT *src = row + (int)vl;
+                            xx[0] = src[0];
+                            xx[1] = src[1];
+                            xx[2] = src[2];
+                            ww[0] = p.absA * sd;
+                            ww[1] = fmaf(-p.absA, fabsf(sd + c1), 1.0f);
+                            ww[2] = fmaxf(fmaf(-p.absA, sd, c3), 0.0f);
+                        };
+                        fetch(0, x[0], w[0]);
+#pragma unroll
+                        for (int b = 0; b < kBinsPerThread; ++b) {
+                            if (b + 1 < kBinsPerThread) fetch(b + 1, x[(b + 1) & 1], w[(b + 1) & 1]);
+                            acc[b] = V::fma(w[b & 1][0], x[b & 1][0], acc[b]);
+                            acc[b] = V::fma(w[b & 1][1], x[b & 1][1], acc[b]);
+                            acc[b] = V::fma(w[b & 1][2], x[b & 1][2], acc[b]);
+                        }
+                    }
+                } else {
+                    for (int r = 0; r < rc; ++r) {
+                        const float vr = fmaf((float)r, p.dv, f00);
+                        const VT *row = base + r * pitch;
+#pragma unroll
+                        for (int b = 0; b < kBinsPerThread; ++b) {
+                            const float vloc = fmaf((float)(4 * b), invA, vr);
+                            const float vl = ceilf(vloc - p.hw);
+                            const float t = vl - vloc;
+                            const VT *src = row + (int)vl;
+                            for (int m = 0; m < p.taps; ++m) {
+                                const float wgt = fmaxf(fmaf(-p.absA, fabsf(t + (float)m), 1.0f), 0.0f);
+                                acc[b] = V::fma(wgt, src[m], acc[b]);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        if (w0 + rows < nw) plan_range(w0 + rows, (s + 1) & 1);
+        __syncthreads();  // the stage's readers are done with tile; the next range is known
     }
 
     // Output through LDS, one slice at a time, so that each wavefront stores
