@@ -241,6 +241,38 @@ def test_preprocess_filter_matches_oracle(xct, case):
     assert err < tol, err
 
 
+# seeded shapes for the persistent front end: N_c a multiple of 4 from 132 to
+# 8192 (every transform length from 256 to 8192), blur radii 0 to 12
+FE_RANDOM = [(int(n_c), int(n_p), int(s), float(sig)) for n_c, n_p, s, sig in zip(
+    np.random.default_rng(2505).integers(33, 2049, 6) * 4,
+    np.random.default_rng(2506).integers(7, 90, 6),
+    np.random.default_rng(2507).integers(1, 4, 6),
+    np.random.default_rng(2508).choice([0.0, 0.4, 1.0, 1.7, 3.0], 6))]
+
+
+@pytest.mark.parametrize("case", range(len(FE_RANDOM)))
+def test_preprocess_filter_seeded_shapes(xct, case):
+    from oracle import pipeline as pl
+
+    n_c, n_p, S, sigma = FE_RANDOM[case]
+    n_r, r0 = S + 1, 1
+    rng = np.random.default_rng(600 + case)
+    g = _geom(n_angles=n_p, n_det=n_c, nx=8, ny=8, det_pitch=1.0)
+    dark, flat = synth.detector_fields(n_r, n_c, 600 + case)
+    lines = torch.as_tensor(rng.uniform(0.0, 3.0, (n_r, n_p, n_c)))
+    proj = synth.raw_counts(lines, dark, flat, 1.0, dtype=torch.uint16)
+    out = torch.empty((S, n_p, n_c), dtype=torch.float32, device="cuda")
+    say("front end seeded", case, n_c, n_p, S, sigma)
+    xct.xct_preprocess_filter(g, proj.view(torch.int16).cuda().view(torch.uint16), dark.cuda(), flat.cuda(),
+                              r0, out, "hann", 1.0, sigma)
+    torch.cuda.synchronize()
+    p = pl.preprocess(proj.numpy().astype(np.float64), dark.numpy(), flat.numpy(), r0, S, 1.0, sigma)
+    ref = oracle.filter(p, g.det_pitch, "hann")
+    err = rel_l2(out.cpu().numpy(), ref)
+    say("  rel L2", err)
+    assert err < 2e-5, err
+
+
 def test_preprocess_filter_persistent_and_fallback_forms_agree(xct):
     """uint16 counts over N_c = 1024 take the persistent front end when the
     stack is 8-byte and the fields 16-byte aligned; the same data through
