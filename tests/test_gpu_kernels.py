@@ -559,6 +559,29 @@ def test_forward_matches_oracle(xct, case, n_slices):
         assert rel_l2(y.cpu().numpy(), ref) < 2e-5
 
 
+# seeded geometries for the forward projector's per-block staging shapes:
+# image sides 40 to 400, 30 to 400 uniform angles, detectors covering the
+# image diagonal, the axis up to 20 bins off the detector centre
+FP_RANDOM = [dict(nx=int(nx), ny=int(ny), n_angles=int(na), off=float(off)) for nx, ny, na, off in zip(
+    np.random.default_rng(3505).integers(40, 401, 4), np.random.default_rng(3506).integers(40, 401, 4),
+    np.random.default_rng(3507).integers(30, 401, 4), np.random.default_rng(3508).uniform(-20, 20, 4))]
+
+
+@pytest.mark.parametrize("case", range(len(FP_RANDOM)))
+def test_forward_seeded_geometries(xct, case):
+    c = FP_RANDOM[case]
+    n_det = int(math.ceil(math.hypot(c["nx"], c["ny"]))) + 3
+    g = _geom(nx=c["nx"], ny=c["ny"], n_angles=c["n_angles"], n_det=n_det,
+              center=(n_det - 1) / 2.0 + c["off"], angles=synth.uniform_angles(c["n_angles"]))
+    rng = np.random.default_rng(700 + case)
+    x = rng.standard_normal((8, c["ny"], c["nx"]))
+    say("fp seeded", case, c, n_det)
+    y = xct.forward_project(to_dev(x), g)
+    torch.cuda.synchronize()
+    ref = oracle.forward(x.astype(np.float32).astype(np.float64), g)
+    assert rel_l2(y.cpu().numpy(), ref) < 2e-5
+
+
 def test_forward_is_deterministic(xct):
     rng = np.random.default_rng(15)
     g = _geom(n_angles=200, n_det=450, nx=300, ny=260, center=230.7)
