@@ -802,10 +802,19 @@ __device__ __forceinline__ void blur_quads(const float *src, float *dst, int nc,
 // Kernel kinds: the front end (raw projection stack); any row form with one
 // workgroup per group of rows; persistent kernels for unshifted, unweighted
 // rows of even length in FP32, FP16 or BF16 that keep the next group's
-// samples in flight; and a persistent front end (uint16 counts, N_c a
-// multiple of 4, stack and fields aligned to quads) that keeps the next
-// group's counts in flight.
-enum { kFrontEnd = 0, kRows = 1, kPersistF32 = 2, kPersistF16 = 3, kPersistBF16 = 4, kPersistFE16 = 5 };
+// samples in flight; a persistent front end (uint16 counts, N_c a multiple
+// of 4, stack and fields aligned to quads) that keeps the next group's counts
+// in flight; and a persistent kernel for FP32 rows of any other form
+// (shifted, weighted, odd lengths, element-wise loads).
+enum {
+    kFrontEnd = 0,
+    kRows = 1,
+    kPersistF32 = 2,
+    kPersistF16 = 3,
+    kPersistBF16 = 4,
+    kPersistFE16 = 5,
+    kPersistAnyF32 = 6
+};
 
 template <int LOG2M, int KIND>
 __global__ __launch_bounds__(256) void filter_fused_kernel(FilterArgs a, int in_t, int out_t)
@@ -813,6 +822,7 @@ __global__ __launch_bounds__(256) void filter_fused_kernel(FilterArgs a, int in_
     constexpr bool FEP = KIND == kPersistFE16;
     constexpr bool PRE = KIND == kFrontEnd || FEP;
     constexpr bool PERSIST = KIND >= kPersistF32;
+    constexpr int LMODE = KIND == kPersistAnyF32 ? 2 : 0;  // load form of the persistent row kinds
     typedef typename std::conditional<KIND == kPersistF16, f16_t,
                                       typename std::conditional<KIND == kPersistBF16, bf16_t, float>::type>::type TP;
     constexpr int M = 1 << LOG2M;
@@ -858,7 +868,7 @@ __global__ __launch_bounds__(256) void filter_fused_kernel(FilterArgs a, int in_
         if (g < groups && r < a.rows) load_raw_quads<TN>(rq, a, r, T_h);
     } else if constexpr (PERSIST) {
         const int64_t r = g * ROWS + rho;
-        if (g < groups && r < a.rows) load_p1<R1, NB1, TN, M, TP, 0>(xn, a, r, T_h);
+        if (g < groups && r < a.rows) load_p1<R1, NB1, TN, M, TP, LMODE>(xn, a, r, T_h);
         else
 #pragma unroll
             for (int i = 0; i < NB1 * H1; ++i) xn[i] = make_float2(0.0f, 0.0f);
@@ -1100,7 +1110,7 @@ __global__ __launch_bounds__(256) void filter_fused_kernel(FilterArgs a, int in_
             if (gn < groups && rn < a.rows) load_raw_quads<TN>(rq, a, rn, T);
         } else if constexpr (PERSIST) {
             const int64_t gn = g + gridDim.x, rn = gn * ROWS + rho;
-            if (gn < groups && rn < a.rows) load_p1<R1, NB1, TN, M, TP, 0>(xn, a, rn, T);
+            if (gn < groups && rn < a.rows) load_p1<R1, NB1, TN, M, TP, LMODE>(xn, a, rn, T);
         }
         __syncthreads();
 
@@ -1324,20 +1334,22 @@ static hipError_t launch_kind(int lg, unsigned n, const FilterArgs &a, int in_t,
 // a buffer aligned to two samples, and front ends from uint16 counts over N_c
 // a multiple of 4 with the stack aligned to 8 bytes and the fields to 16, take a
 // persistent kernel: two workgroups per CU (as many as the LDS holds), each
-// walking its groups of rows with the next group's samples in flight.  Other
-// rows take a workgroup per group (at most 2^32 - 1 work-items: N_c <= 8192
-// keeps the groups of any valid call below that).
+// walking its groups of rows with the next group's samples in flight; so do
+// FP32 rows of any other form (shifted, weighted, odd), loaded sample by
+// sample.  Other rows take a workgroup per group (at most 2^32 - 1
+// work-items: N_c <= 8192 keeps the groups of any valid call below that).
 static hipError_t launch_fused(const FilterArgs &a, bool pre, int in_t, int out_t, hipStream_t s)
 {
     const int lg = a.log2L - 1;  // log2 M
     const int rows_per_wg = 8192 >> lg;
     const int64_t wgs = (a.rows + rows_per_wg - 1) / rows_per_wg;
     const size_t esz = in_t == XCT_F32 ? 4 : 2;
+    const bool plain = !a.weight && a.in_first == 0 && (a.in_len & 1) == 0 &&
+                       reinterpret_cast<uintptr_t>(a.in) % (2 * esz) == 0;
     const bool persist = pre ? in_t == XCT_U16 && (a.nc & 3) == 0 && reinterpret_cast<uintptr_t>(a.in) % 8 == 0 &&
                                    reinterpret_cast<uintptr_t>(a.pre.dark) % 16 == 0 &&
                                    reinterpret_cast<uintptr_t>(a.pre.flat) % 16 == 0
-                             : !a.weight && a.in_first == 0 && (a.in_len & 1) == 0 &&
-                                   reinterpret_cast<uintptr_t>(a.in) % (2 * esz) == 0;
+                             : plain || in_t == XCT_F32;
     const int64_t cap = persist ? 2 * (int64_t)device_cus() : (((int64_t)1 << 32) - 1) / 256;
     if (!persist && wgs > cap) return hipErrorInvalidConfiguration;
     const unsigned n = (unsigned)(wgs < cap ? wgs : cap);
@@ -1345,6 +1357,7 @@ static hipError_t launch_fused(const FilterArgs &a, bool pre, int in_t, int out_
     if (pre && persist) return launch_kind<kPersistFE16>(lg, n, a, in_t, out_t, s);
     if (pre) return launch_kind<kFrontEnd>(lg, n, a, in_t, out_t, s);
     if (!persist) return launch_kind<kRows>(lg, n, a, in_t, out_t, s);
+    if (!plain) return launch_kind<kPersistAnyF32>(lg, n, a, in_t, out_t, s);
     if (in_t == XCT_F32) return launch_kind<kPersistF32>(lg, n, a, in_t, out_t, s);
     if (in_t == XCT_F16) return launch_kind<kPersistF16>(lg, n, a, in_t, out_t, s);
     return launch_kind<kPersistBF16>(lg, n, a, in_t, out_t, s);
