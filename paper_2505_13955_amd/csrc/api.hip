@@ -26,6 +26,26 @@ int hip_fail(hipError_t e)
     return XCT_EHIP;
 }
 
+// Stream-ordered scratch of the forward projector's four-slice copies: at
+// most this much per chunk, and the device's default pool keeps up to this
+// much between calls instead of returning it at each synchronisation.
+constexpr int64_t kQuadBytes = (int64_t)1 << 30;
+
+void keep_stream_pool()
+{
+    static std::mutex m;
+    static std::vector<int> done;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lock(m);
+    if (std::find(done.begin(), done.end(), dev) != done.end()) return;
+    done.push_back(dev);
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) != hipSuccess) return;
+    uint64_t keep = (uint64_t)kQuadBytes;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+}
+
 bool dtype_ok(int t) { return t == XCT_F32 || t == XCT_F16 || t == XCT_BF16; }
 size_t dtype_size(int t) { return t == XCT_F32 ? 4 : 2; }
 
@@ -859,7 +879,37 @@ int xct_forward_project(const xct_geometry *g, int32_t n_slices, const float *im
     a.nx = g->nx;
     a.ny = g->ny;
     a.n_slices = n_slices;
-    hipError_t e = launch_forward(a, sl, s);
+    if (sl == 1) {
+        const hipError_t e = launch_forward(a, 1, s);
+        return e == hipSuccess ? XCT_OK : hip_fail(e);
+    }
+    // Four slices per workgroup read four-slice copies of the image and of
+    // its transpose, made chunk by chunk of slice groups in stream-ordered
+    // memory (kQuadBytes, or one group when a group needs more).
+    const int64_t plane = (int64_t)g->nx * g->ny;
+    const int64_t group_bytes = 2 * plane * (int64_t)sizeof(float4);
+    const int64_t groups = (n_slices + 3) / 4;
+    const int64_t per = std::max<int64_t>(1, std::min<int64_t>(groups, kQuadBytes / group_bytes));
+    keep_stream_pool();
+    void *buf = nullptr;
+    hipError_t e = hipMallocAsync(&buf, (size_t)(per * group_bytes), s);
+    if (e != hipSuccess) return hip_fail(e);
+    float4 *quad = static_cast<float4 *>(buf), *quad_t = quad + per * plane;
+    for (int64_t g0 = 0; g0 < groups && e == hipSuccess; g0 += per) {
+        const int64_t z = 4 * g0;
+        const int ns = (int)std::min<int64_t>(n_slices - z, 4 * per);
+        e = launch_forward_quads(image + z * plane, ns, g->nx, g->ny, quad, quad_t, s);
+        if (e != hipSuccess) break;
+        FPArgs c = a;
+        c.image = image + z * plane;
+        c.sino = sino + z * (int64_t)g->n_angles * g->n_det;
+        c.n_slices = ns;
+        c.quad = quad;
+        c.quad_t = quad_t;
+        e = launch_forward(c, 4, s);
+    }
+    const hipError_t f = hipFreeAsync(buf, s);
+    if (e == hipSuccess) e = f;
     return e == hipSuccess ? XCT_OK : hip_fail(e);
 }
 

@@ -13,7 +13,10 @@
 // image a few steps at a time: it stages into LDS, with coalesced reads, the
 // rectangle of pixels those strips can touch (zeros outside the image), then
 // every thread adds its taps for its 16 bins, and at the end the results go
-// out through LDS so that the stores run along bins.  Each XCD takes a
+// out through LDS so that the stores run along bins.  Four slices per
+// workgroup read their pixels from a copy of the image with the four slices'
+// values side by side, and blocks walking columns from its transpose, so that
+// a stage is read along image rows one 16-byte pixel per load.  Each XCD takes a
 // contiguous run of (slice group, bin block, angle block) triples, angle
 // blocks fastest, so that the workgroups sharing an L2 stage overlapping
 // rectangles of the same slices.  Per stage a thread
@@ -100,6 +103,9 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
     const int nb = n0 + wave * 64 + (lane >> 4);  // this thread's first bin; its bins are nb + 4 b
     const int64_t plane = (int64_t)a.nx * a.ny;
     const float *img = a.image + (int64_t)z0 * plane;
+    // four slices: this group's pixels, read along the walk steps' rows
+    const float4 *quad = SL == 4 ? (walk ? a.quad_t : a.quad) + (int64_t)(z0 >> 2) * plane : nullptr;
+    const int quad_ld = walk ? a.ny : a.nx;
     const int rows = B.rows[SL == 4 ? 1 : 0], pitch = B.pitch[SL == 4 ? 1 : 0];
     const bool on = q < count;
     const FPAngle p = a.ang[k0 + (on ? q : 0)];
@@ -150,9 +156,11 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
         const bool stage_on = vlo + width > 0 && vlo < nv;  // the strips reach the image here
         if (stage_on) {
             // Stage walk steps w0 .. w0+rc-1, cross indices vlo .. vlo+width-1,
-            // as a flat range of pixels, several in flight per thread.  Walking
-            // rows, consecutive pixels run along an image row; walking columns,
-            // `rows` consecutive columns of one image row are read together.
+            // as a flat range of pixels, several in flight per thread.  Four
+            // slices and single slices walking rows read consecutive pixels
+            // along a row (of the transposed copy when walking columns); a
+            // single slice walking columns reads `rows` consecutive columns of
+            // one image row together.
             // (f + 1/2) / width in FP32 recovers the staged row of pixel f
             // exactly: the quotient is below 16, its rounding error below 2^-19,
             // and its distance to an integer at least 1/(2 width) >= 2^-14; and
@@ -160,7 +168,8 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
             // rounding error below 2^-10, its distance to an integer at least
             // 1/(2 rows) >= 2^-5.
             {
-                const int total = walk ? width * rows : width * rc;
+                const bool by_rows = SL == 4 || walk == 0;
+                const int total = by_rows ? width * rc : width * rows;
                 const float invw = 1.0f / (float)width, invr = 1.0f / (float)rows;
                 for (int fb = 0; fb < total; fb += kStageBatch * kFPBins) {
                     VT val[kStageBatch];
@@ -169,7 +178,7 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
                     for (int i = 0; i < kStageBatch; ++i) {
                         const int f = fb + i * kFPBins + tid;
                         int r, c;
-                        if (walk == 0) {
+                        if (by_rows) {
                             r = (int)(((float)f + 0.5f) * invw);
                             c = f - r * width;
                         } else {
@@ -177,16 +186,14 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
                             r = f - c * rows;
                         }
                         const int v = vlo + c;
-                        float x[SL];
-#pragma unroll
-                        for (int sl = 0; sl < SL; ++sl) x[sl] = 0.0f;
-                        if (f < total && r < rc && v >= 0 && v < nv) {
-                            const int64_t off = walk ? (int64_t)v * a.nx + w0 + r : (int64_t)(w0 + r) * a.nx + v;
-#pragma unroll
-                            for (int sl = 0; sl < SL; ++sl)
-                                if (sl < nsl) x[sl] = img[sl * plane + off];
+                        const bool in = f < total && r < rc && v >= 0 && v < nv;
+                        if constexpr (SL == 4) {
+                            val[i] = in ? quad[(int64_t)(w0 + r) * quad_ld + v] : V::zero();
+                        } else {
+                            float x = 0.0f;
+                            if (in) x = img[walk ? (int64_t)v * a.nx + w0 + r : (int64_t)(w0 + r) * a.nx + v];
+                            val[i] = x;
                         }
-                        val[i] = V::pack(x);
                         dst[i] = f < total ? r * pitch + c : -1;
                     }
 #pragma unroll
@@ -292,6 +299,46 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
             }
         }
     }
+}
+
+// Four-slice copies of the image for fp_tile_kernel<4>: for slice group g
+// (slices 4g .. 4g+3, zero past the last slice) quad[g][y][x] holds the four
+// values of pixel (x, y) and quad_t[g][x][y] the same.  32 x 32 pixels per
+// workgroup, transposed through LDS.
+__global__ __launch_bounds__(256) void fp_quad_kernel(const float *img, int n_slices, int nx, int ny, float4 *quad,
+                                                      float4 *quad_t)
+{
+    __shared__ float4 t[32][33];
+    const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32, g = blockIdx.z;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int64_t plane = (int64_t)nx * ny;
+#pragma unroll
+    for (int j = ty; j < 32; j += 8) {
+        const int x = x0 + tx, y = y0 + j;
+        float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (x < nx && y < ny) {
+#pragma unroll
+            for (int sl = 0; sl < 4; ++sl)
+                if (4 * g + sl < n_slices) v[sl] = img[(int64_t)(4 * g + sl) * plane + (int64_t)y * nx + x];
+            quad[g * plane + (int64_t)y * nx + x] = make_float4(v[0], v[1], v[2], v[3]);
+        }
+        t[j][tx] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = ty; j < 32; j += 8) {
+        const int x = x0 + j, y = y0 + tx;
+        if (x < nx && y < ny) quad_t[g * plane + (int64_t)x * ny + y] = t[tx][j];
+    }
+}
+
+hipError_t launch_forward_quads(const float *image, int n_slices, int nx, int ny, float4 *quad, float4 *quad_t,
+                                hipStream_t s)
+{
+    (void)hipGetLastError();
+    const dim3 grid((unsigned)((nx + 31) / 32), (unsigned)((ny + 31) / 32), (unsigned)((n_slices + 3) / 4));
+    hipLaunchKernelGGL(fp_quad_kernel, grid, dim3(256), 0, s, image, n_slices, nx, ny, quad, quad_t);
+    return hipGetLastError();
 }
 
 hipError_t launch_forward(const FPArgs &a, int sl, hipStream_t s)

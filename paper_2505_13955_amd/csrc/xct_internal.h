@@ -146,6 +146,7 @@ static_assert(4 * kFPAngles <= 64, "angle block larger than one wavefront's corn
 
 struct FPArgs {
     const float *image;  // [S][Ny][Nx]
+    const float4 *quad, *quad_t;  // four slices per workgroup: [S/4][Ny][Nx] and [S/4][Nx][Ny]
     float *sino;         // [S][Np][Nc]
     const FPAngle *ang;  // [Np]
     const FPBlock *blocks;
@@ -159,8 +160,11 @@ struct FPArgs {
 // some block has no one-slice shape; *four tells whether every block has a
 // four-slice shape).
 int fp_plan(const xct_geometry *g, std::vector<FPAngle> &ang, std::vector<FPBlock> &blocks, bool *four);
-// `sl`: slices per workgroup, 1 or 4.
+// `sl`: slices per workgroup, 1 or 4 (four read a.quad and a.quad_t, written
+// by launch_forward_quads from the same image).
 hipError_t launch_forward(const FPArgs &a, int sl, hipStream_t s);
+hipError_t launch_forward_quads(const float *image, int n_slices, int nx, int ny, float4 *quad, float4 *quad_t,
+                                hipStream_t s);
 
 hipError_t launch_reduce(const float *a, const float *b, int64_t n, double *result,
                          double *partials, int nblocks, int sqdist, hipStream_t s);
