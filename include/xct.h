@@ -208,9 +208,15 @@ int xct_backproject_u16(const xct_geometry *g, int32_t n_slices, const void *sin
  * forward model only to simulate scans for training data (Section V-B); this
  * operator is the differentiable pair's forward half.
  *   image  device [n_slices][N_y][N_x] FP32;  sino  device [n_slices][N_p][N_c] FP32
+ * Three or more slices are projected four at a time from copies of the image
+ * with the four slices' values side by side (and a transposed copy), made on
+ * the stream in stream-ordered device memory: 32 N_x N_y bytes per group of
+ * four slices, at most 1 GiB per chunk of groups (one group when a group
+ * needs more), freed on the stream before the call returns.
  * Deterministic (gather form, no atomics).  Errors: XCT_EINVAL for
  * non-finite alpha, XCT_ETOOBIG beyond 65535 slices or 2^31 workgroups
- * (one per group of four slices, 256 bins and up to 16 angles). */
+ * (one per group of four slices, 256 bins and up to 16 angles), XCT_EHIP
+ * when the copies cannot be allocated. */
 int xct_forward_project(const xct_geometry *g, int32_t n_slices, const float *image,
                         float *sino, float alpha, int32_t accumulate, xct_stream stream);
 
