@@ -559,6 +559,24 @@ def test_forward_matches_oracle(xct, case, n_slices):
         assert rel_l2(y.cpu().numpy(), ref) < 2e-5
 
 
+def test_forward_project_in_chunks_of_slice_groups(xct):
+    """Eleven slices of 4096^2: a group of four slices needs 512 MiB of
+    four-slice copies, so the call works in two chunks (two groups, then a
+    partial group of three slices).  Slices on both sides of the chunk
+    boundary and the partial group are checked against the oracle."""
+    n, na, nd = 4096, 8, 5795
+    g = _geom(nx=n, ny=n, n_angles=na, n_det=nd, det_pitch=1.0, pixel_size=1.0, center=(nd - 1) / 2,
+              angles=synth.uniform_angles(na))
+    rng = np.random.default_rng(4096)
+    x = rng.standard_normal((11, n, n), dtype=np.float32)
+    say("fp chunks", n, na, nd, 11)
+    y = xct.forward_project(to_dev(x), g)
+    torch.cuda.synchronize()
+    for s in (0, 7, 8, 10):
+        ref = oracle.forward(x[s:s + 1].astype(np.float64), g)
+        assert rel_l2(y[s:s + 1].cpu().numpy(), ref) < 2e-5, s
+
+
 # seeded geometries for the forward projector's per-block staging shapes:
 # image sides 40 to 400, 30 to 400 uniform angles, detectors covering the
 # image diagonal, the axis up to 20 bins off the detector centre
