@@ -69,6 +69,21 @@ def test_filter_storage_types(xct, sin_t, sout_t):
         assert torch.equal(q32.to(sout_t), q)
 
 
+@pytest.mark.parametrize("sout_t", [torch.float16, torch.bfloat16])
+def test_filter_odd_rows_reduced_output(xct, sout_t):
+    """FP32 rows of odd length (the persistent kernel's sample-by-sample form)
+    stored as FP16 / BF16: the FP32 result rounded to the storage type."""
+    rng = np.random.default_rng(301)
+    p = rng.standard_normal((3, 7, 301)) * 5
+    g = _geom(n_angles=7, n_det=301, nx=4, ny=4)
+    say("filter odd rows", sout_t)
+    q32 = xct.filter(to_dev(p), g, "hann")
+    q = xct.filter(to_dev(p), g, "hann", out_dtype=sout_t)
+    torch.cuda.synchronize()
+    assert rel_l2(q32.cpu().numpy(), oracle.filter(p.astype(np.float32).astype(np.float64), 1.0, "hann")) < 5e-6
+    assert torch.equal(q32.to(sout_t), q)
+
+
 def test_filter_in_place(xct):
     rng = np.random.default_rng(6)
     p = rng.standard_normal((1, 8, 100))
