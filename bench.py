@@ -355,7 +355,7 @@ def measure_adjoint_pair(xct, torch, configs, stream, steps, warmup):
         "transpose_ms": bp_ms, "transpose_gups": updates / (bp_ms * 1e-3) / 1e9,
         "ls_gradient_ms": gr_ms, "ls_gradient_gups": 2 * updates / (gr_ms * 1e-3) / 1e9,
         "updates_per_operator": updates,
-        "roofline_forward": _alu_roofline("fp_tile_kernel<4>", updates, fp_ms),
+        "roofline_forward": _alu_roofline("fp_quad_kernel + fp_tile_kernel<4> (whole call)", updates, fp_ms),
     }
 
 
