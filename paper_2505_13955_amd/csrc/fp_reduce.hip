@@ -64,11 +64,14 @@ template <> struct FPVec<4> {
 
 // Lanes of a wavefront: 16 angles of the block x 4 bin groups; group g of
 // wavefront v takes bins 64 v + g + 4 b, b < 16, of the block, and a thread
-// accumulates its angle's 16 bins for SL slices.  Lanes that read together
-// are the block's angles at four adjacent bins, whose taps lie within a few
-// pixels of each other (often at the same address).  With groups of 16
-// consecutive bins the four groups' taps sat about 16 pixels (16 entries of
-// 16 bytes) apart, on the same LDS banks, and the kernel ran 8 % slower.
+// accumulates its angle's 16 bins for SL slices.  Lane 4 q + g takes angle
+// q and group g, so each 16 lanes that a 16-byte LDS read serves together
+// hold four neighbouring angles at four adjacent bins, whose taps lie within
+// a few entries of each other (often at the same address) and so on distinct
+// banks.  With the 16 angles of one bin in those 16 lanes, the angles' taps
+// spread past 16 entries (the same banks) toward the image edges: 17 times
+// the bank-conflict cycles.  With groups of 16 consecutive bins the groups'
+// taps sat about 16 entries apart, and the kernel ran 8 % slower.
 template <int SL>
 __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
 {
@@ -83,7 +86,7 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
     __shared__ int2 range[2];  // per stage (first staged cross index, staged width), two in turn
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int q = lane & 15;                       // angle of the block
+    const int q = lane >> 2;                       // angle of the block
     // workgroup i of a launch runs on XCD i mod 8: give each XCD a
     // contiguous run of (slice group, bin block, angle block) triples, angle
     // block fastest, so the workgroups of one XCD stage overlapping pixels
@@ -100,7 +103,7 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
     const int nv = walk ? a.ny : a.nx, nw = walk ? a.nx : a.ny;
     const int n0 = bb * kFPBins;
     const int n1 = n0 + kFPBins - 1;  // the plan sizes stages for whole bin blocks
-    const int nb = n0 + wave * 64 + (lane >> 4);  // this thread's first bin; its bins are nb + 4 b
+    const int nb = n0 + wave * 64 + (lane & 3);   // this thread's first bin; its bins are nb + 4 b
     const int64_t plane = (int64_t)a.nx * a.ny;
     const float *img = a.image + (int64_t)z0 * plane;
     // four slices: this group's pixels, read along the walk steps' rows
