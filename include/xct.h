@@ -220,6 +220,16 @@ int xct_backproject_u16(const xct_geometry *g, int32_t n_slices, const void *sin
 int xct_forward_project(const xct_geometry *g, int32_t n_slices, const float *image,
                         float *sino, float alpha, int32_t accumulate, xct_stream stream);
 
+/* Residual form of xct_forward_project for the least-squares gradient:
+ *   r[s][k][n] = y[s][k][n] + alpha (P image[s])[k][n]
+ * (alpha = -1 gives r = y - P x), formed as one FP32 multiply-add per
+ * element in the projector's store, so y is read once and needs no copy.
+ *   image device [n_slices][N_y][N_x] FP32; y, r device [n_slices][N_p][N_c]
+ *   FP32 (r may be y itself, updated in place).
+ * Errors and memory use as xct_forward_project; XCT_EINVAL for a null y. */
+int xct_forward_residual(const xct_geometry *g, int32_t n_slices, const float *image, const float *y,
+                         float *r, float alpha, xct_stream stream);
+
 /* Transpose of xct_forward_project (the back-projector scaled by
  * pixel^2 / pitch), the backward half of the differentiable pair:
  *   image[s] = (accumulate ? image[s] : 0) + alpha (P^T sino[s])

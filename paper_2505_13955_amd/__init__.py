@@ -32,6 +32,7 @@ from .xct import (  # noqa: F401
     xct_filter,
     xct_filter_offset,
     xct_forward_project,
+    xct_forward_residual,
     xct_project_adjoint,
     xct_offset_detector,
     xct_preprocess_filter,

@@ -59,9 +59,9 @@ def project(x: torch.Tensor, geom, chunk: int | None = None) -> torch.Tensor:
 def ls_loss_and_grad(x: torch.Tensor, y: torch.Tensor, geom, chunk: int | None = None):
     """(||P x - y||^2 as a float64 device scalar, 2 P^T (P x - y) as FP32),
     computed chunk by chunk of slices, holding one chunk's residual at a time.
-    The residual is formed inside the forward projector, which accumulates
-    -P x onto a copy of y (r = y - P x); the loss is an FP64 reduction of r and
-    the gradient one back-projection, -2 P^T r."""
+    The residual r = y - P x is formed inside the forward projector's store
+    (one multiply-add per element, y read once); the loss is an FP64
+    reduction of r and the gradient one back-projection, -2 P^T r."""
     chunk = chunk or default_chunk(geom)
     x = x.contiguous()
     y = y.contiguous()
@@ -72,8 +72,7 @@ def ls_loss_and_grad(x: torch.Tensor, y: torch.Tensor, geom, chunk: int | None =
     for s0 in range(0, S, chunk):
         s1 = min(s0 + chunk, S)
         r = res[: s1 - s0]
-        r.copy_(y[s0:s1])
-        xct.xct_forward_project(geom, x[s0:s1], r, -1.0, accumulate=True)
+        xct.xct_forward_residual(geom, x[s0:s1], y[s0:s1], r, -1.0)
         loss += xct.xct_dot_f64(r, r)
         xct.xct_project_adjoint(geom, r, grad[s0:s1], -2.0)
     return loss, grad

@@ -849,8 +849,11 @@ int xct_backproject_u16(const xct_geometry *g, int32_t n_slices, const void *sin
 // P = (pixel^2 / pitch) A, the projector of the least-squares problem.
 static double projector_scale(const xct_geometry *g) { return g->pixel_size * g->pixel_size / g->det_pitch; }
 
-int xct_forward_project(const xct_geometry *g, int32_t n_slices, const float *image, float *sino,
-                        float alpha, int32_t accumulate, xct_stream stream)
+}  // extern "C"
+
+// sino = (base ? base : accumulate ? sino : 0) + alpha P image.
+static int forward_project(const xct_geometry *g, int32_t n_slices, const float *image, const float *base,
+                           float *sino, float alpha, int32_t accumulate, xct_stream stream)
 {
     if (int rc = check_geometry(g, true)) return rc;
     if (int rc = check_slices(g, n_slices)) return rc;
@@ -863,6 +866,7 @@ int xct_forward_project(const xct_geometry *g, int32_t n_slices, const float *im
     FPArgs a{};
     a.image = image;
     a.sino = sino;
+    a.base = base;
     a.ang = t->table<FPAngle>(0);
     a.blocks = t->table<FPBlock>(1);
     a.n_blocks = t->n_blocks;
@@ -903,6 +907,7 @@ int xct_forward_project(const xct_geometry *g, int32_t n_slices, const float *im
         FPArgs c = a;
         c.image = image + z * plane;
         c.sino = sino + z * (int64_t)g->n_angles * g->n_det;
+        if (base) c.base = base + z * (int64_t)g->n_angles * g->n_det;
         c.n_slices = ns;
         c.quad = quad;
         c.quad_t = quad_t;
@@ -911,6 +916,21 @@ int xct_forward_project(const xct_geometry *g, int32_t n_slices, const float *im
     const hipError_t f = hipFreeAsync(buf, s);
     if (e == hipSuccess) e = f;
     return e == hipSuccess ? XCT_OK : hip_fail(e);
+}
+
+extern "C" {
+
+int xct_forward_project(const xct_geometry *g, int32_t n_slices, const float *image, float *sino,
+                        float alpha, int32_t accumulate, xct_stream stream)
+{
+    return forward_project(g, n_slices, image, nullptr, sino, alpha, accumulate, stream);
+}
+
+int xct_forward_residual(const xct_geometry *g, int32_t n_slices, const float *image, const float *y,
+                         float *r, float alpha, xct_stream stream)
+{
+    if (!y) return XCT_EINVAL;
+    return forward_project(g, n_slices, image, y, r, alpha, 0, stream);
 }
 
 int xct_project_adjoint(const xct_geometry *g, int32_t n_slices, const float *sino, float *image,

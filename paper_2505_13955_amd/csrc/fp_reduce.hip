@@ -294,11 +294,14 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
         __syncthreads();
         const int n = n0 + tid;
         if (n < a.n_det) {
-            float *out = a.sino + ((int64_t)(z0 + sl) * a.n_angles + k0) * a.n_det + n;
+            const int64_t row0 = ((int64_t)(z0 + sl) * a.n_angles + k0) * a.n_det + n;
+            float *out = a.sino + row0;
+            const float *base = a.base ? a.base + row0 : nullptr;
             for (int qq = 0; qq < count; ++qq) {
                 const float v = out_lds[qq * kOutPitch + tid];
                 float *o = out + (int64_t)qq * a.n_det;
-                *o = a.accumulate ? fmaf(a.scale, v, *o) : a.scale * v;
+                if (base) *o = fmaf(a.scale, v, base[(int64_t)qq * a.n_det]);
+                else *o = a.accumulate ? fmaf(a.scale, v, *o) : a.scale * v;
             }
         }
     }

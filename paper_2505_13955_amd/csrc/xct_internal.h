@@ -148,6 +148,7 @@ struct FPArgs {
     const float *image;  // [S][Ny][Nx]
     const float4 *quad, *quad_t;  // four slices per workgroup: [S/4][Ny][Nx] and [S/4][Nx][Ny]
     float *sino;         // [S][Np][Nc]
+    const float *base;   // [S][Np][Nc] added to the scaled projection, or nullptr
     const FPAngle *ang;  // [Np]
     const FPBlock *blocks;
     int32_t n_blocks, bin_blocks;

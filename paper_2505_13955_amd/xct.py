@@ -67,6 +67,7 @@ EXPORTS = (
     "xct_backproject",
     "xct_backproject_u16",
     "xct_forward_project",
+    "xct_forward_residual",
     "xct_project_adjoint",
     "xct_fbp_workspace_bytes",
     "xct_fbp_batch",
@@ -105,6 +106,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "xct_backproject_u16": ([gp, i32, vp, i32, vp, ctypes.c_float, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_double, vp], ctypes.c_int),
         "xct_forward_project": ([gp, i32, vp, vp, ctypes.c_float, i32, vp], ctypes.c_int),
+        "xct_forward_residual": ([gp, i32, vp, vp, vp, ctypes.c_float, vp], ctypes.c_int),
         "xct_project_adjoint": ([gp, i32, vp, vp, ctypes.c_float, i32, vp], ctypes.c_int),
         "xct_fbp_workspace_bytes": ([sp, i32, i32], sz),
         "xct_fbp_batch": ([sp, i32, i32, i32, i32, vp, sz, vp], ctypes.c_int),
@@ -279,6 +281,19 @@ def xct_forward_project(geom, image: torch.Tensor, sino: torch.Tensor, alpha: fl
     rc = lib.xct_forward_project(ctypes.byref(g), S, p_in, p_out, float(alpha), 1 if accumulate else 0,
                                  _stream(image))
     _check("xct_forward_project", rc)
+
+
+def xct_forward_residual(geom, image: torch.Tensor, y: torch.Tensor, r: torch.Tensor,
+                         alpha: float = -1.0) -> None:
+    """r = y + alpha * P image (alpha = -1: the residual y - P x)."""
+    lib = load_library()
+    S = _slices(image, geom, True)
+    p_in = _dev(image, "image", (torch.float32,))
+    p_y = _dev(y, "y", (torch.float32,), (S, geom.n_angles, geom.n_det))
+    p_r = _dev(r, "r", (torch.float32,), (S, geom.n_angles, geom.n_det))
+    g, ang = make_geometry(geom)
+    rc = lib.xct_forward_residual(ctypes.byref(g), S, p_in, p_y, p_r, float(alpha), _stream(image))
+    _check("xct_forward_residual", rc)
 
 
 def xct_project_adjoint(geom, sino: torch.Tensor, image: torch.Tensor, alpha: float = 1.0,

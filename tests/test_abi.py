@@ -101,6 +101,10 @@ def test_backproject_validation(lib):
     assert lib.xct_forward_project(ctypes.byref(g), 70000, FAKE, FAKE, 1.0, 0, None) == ETOOBIG
     assert lib.xct_forward_project(ctypes.byref(g), 1, FAKE, FAKE, float("inf"), 0, None) == EINVAL
     assert lib.xct_forward_project(ctypes.byref(g), 1, None, FAKE, 1.0, 0, None) == EINVAL
+    assert lib.xct_forward_residual(ctypes.byref(g), 1, FAKE, None, FAKE, -1.0, None) == EINVAL
+    assert lib.xct_forward_residual(ctypes.byref(g), 1, None, FAKE, FAKE, -1.0, None) == EINVAL
+    assert lib.xct_forward_residual(ctypes.byref(g), 1, FAKE, FAKE, FAKE, float("nan"), None) == EINVAL
+    assert lib.xct_forward_residual(ctypes.byref(g), 70000, FAKE, FAKE, FAKE, -1.0, None) == ETOOBIG
     assert lib.xct_project_adjoint(ctypes.byref(g), 1, FAKE, FAKE, float("nan"), 0, None) == EINVAL
     assert lib.xct_project_adjoint(ctypes.byref(g), 1, FAKE, None, 1.0, 0, None) == EINVAL
     assert lib.xct_project_adjoint(ctypes.byref(g), 0, FAKE, FAKE, 1.0, 0, None) == EINVAL

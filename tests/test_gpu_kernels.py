@@ -574,6 +574,31 @@ def test_forward_matches_oracle(xct, case, n_slices):
         assert rel_l2(y.cpu().numpy(), ref) < 2e-5
 
 
+@pytest.mark.parametrize("n_slices", [2, 7])
+def test_forward_residual_equals_accumulated_projection(xct, n_slices):
+    """r = y - P x from the residual entry point equals y copied and then
+    accumulated with alpha = -1, bit for bit (one FP32 multiply-add per
+    element either way), written to another buffer and in place."""
+    c = dict(FP_CASES[6])
+    c["angles"] = synth.uniform_angles(c["n_angles"])
+    g = _geom(**c)
+    rng = np.random.default_rng(77)
+    x = to_dev(rng.standard_normal((n_slices, g.ny, g.nx)))
+    y = to_dev(rng.standard_normal((n_slices, g.n_angles, g.n_det)))
+    say("fp residual", n_slices)
+    want = y.clone()
+    xct.xct_forward_project(g, x, want, -1.0, accumulate=True)
+    r = torch.empty_like(y)
+    xct.xct_forward_residual(g, x, y, r, -1.0)
+    inplace = y.clone()
+    xct.xct_forward_residual(g, x, inplace, inplace, -1.0)
+    torch.cuda.synchronize()
+    assert torch.equal(r, want)
+    assert torch.equal(inplace, want)
+    ref = y.double().cpu().numpy() - oracle.forward(x.double().cpu().numpy(), g)
+    assert rel_l2(r.cpu().numpy(), ref) < 2e-5
+
+
 def test_forward_project_in_chunks_of_slice_groups(xct):
     """Eleven slices of 4096^2: a group of four slices needs 512 MiB of
     four-slice copies, so the call works in two chunks (two groups, then a
