@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
     };
 
     // Stages in turn: the next stage's cross range is formed while the
-    // current stage's readers finish, so a stage takes two barriers.
+    // current stage is added up, so a stage takes two barriers.
     plan_range(0, 0);
     __syncthreads();
     for (int s = 0, w0 = 0; w0 < nw; ++s, w0 += rows) {
@@ -205,7 +205,10 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
                 }
             }
         }
-        __syncthreads();  // the stage is in tile
+        __syncthreads();  // the stage is in tile; every wavefront has read its range
+        // wavefront 0 forms the next stage's range first, so that its
+        // latency hides behind its own taps rather than delaying the barrier
+        if (w0 + rows < nw) plan_range(w0 + rows, (s + 1) & 1);
         if (stage_on) {
             // This thread's crossings: v*(nb + 4b, w0 + r) - vlo = rel0 + 4b/A + r dv,
             // anchored once per stage in FP64 (integer part bi0, FP32 fraction f00)
@@ -276,7 +279,6 @@ __global__ __launch_bounds__(kFPBins, 4) void fp_tile_kernel(FPArgs a)
                 }
             }
         }
-        if (w0 + rows < nw) plan_range(w0 + rows, (s + 1) & 1);
         __syncthreads();  // the stage's readers are done with tile; the next range is known
     }
 
