@@ -615,6 +615,16 @@ def test_forward_project_in_chunks_of_slice_groups(xct):
     for s in (0, 7, 8, 10):
         ref = oracle.forward(x[s:s + 1].astype(np.float64), g)
         assert rel_l2(y[s:s + 1].cpu().numpy(), ref) < 2e-5, s
+    # the residual form over the same two chunks: bit for bit the
+    # accumulated projection (each chunk reads y at its own slices)
+    xd = to_dev(x)
+    yb = to_dev(rng.standard_normal((11, na, nd)))
+    r = torch.empty_like(yb)
+    xct.xct_forward_residual(g, xd, yb, r, -1.0)
+    want = yb.clone()
+    xct.xct_forward_project(g, xd, want, -1.0, accumulate=True)
+    torch.cuda.synchronize()
+    assert torch.equal(r, want)
 
 
 # seeded geometries for the forward projector's per-block staging shapes:
