@@ -212,7 +212,9 @@ int xct_backproject_u16(const xct_geometry *g, int32_t n_slices, const void *sin
  * with the four slices' values side by side (and a transposed copy), made on
  * the stream in stream-ordered device memory: 32 N_x N_y bytes per group of
  * four slices, at most 1 GiB per chunk of groups (one group when a group
- * needs more), freed on the stream before the call returns.
+ * needs more), freed on the stream before the call returns; the first such
+ * call on a device sets that device's default memory pool to keep up to
+ * 1 GiB of freed memory between calls.
  * Deterministic (gather form, no atomics).  Errors: XCT_EINVAL for
  * non-finite alpha, XCT_ETOOBIG beyond 65535 slices or 2^31 workgroups
  * (one per group of four slices, 256 bins and up to 16 angles), XCT_EHIP
