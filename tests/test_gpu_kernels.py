@@ -34,7 +34,7 @@ def _geom(**kw):
 
 # ---------------------------------------------------------------- filter
 @pytest.mark.parametrize("window", ["ram_lak", "shepp_logan", "hann"])
-@pytest.mark.parametrize("nc", [1, 2, 7, 64, 100, 367, 1000, 1500, 2900, 8192])
+@pytest.mark.parametrize("nc", [1, 2, 7, 64, 100, 367, 701, 1000, 1500, 1501, 2900, 4095, 5001, 8192])
 def test_filter_matches_oracle(xct, window, nc):
     rng = np.random.default_rng(nc)
     rows = 5 if nc >= 2900 else 9
